@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark of the P2M++ query stage on one MI355X.
+
+Workload: displaced icosphere split 7 times (327,680 triangles), 10M query
+points (5M uniform in the mesh box x1.2, 5M near-surface with sigma = 0.5% of
+the box diagonal), float32.  Preprocessing (p2m_build) is excluded; inputs
+are resident in HBM when timing starts.
+
+One step = one forward pass over all 10M points: the query sort
+(p2m_sort_points) followed by the search kernel (p2m_query_ordered), the two
+halves of p2m_query.  HIP events on the stream the kernels run on time both
+halves of every step.  Forward+backward and fused forward+backward are timed
+the same way after the forward steps and reported as extra fields.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "device.h"):
+        with open(os.path.join(ROOT, "paper_2605_00429_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_hash, n_points):
+    """HBM traffic of the search kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "search_kernel_c2_10M_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash or t.get("n_points") != n_points:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def bytes_per_query(ctr, n):
+    """Algorithmic bytes one query touches (each touch counted once):
+    point 12, order 4, seed cell 4, per visited site 32 (position + ranges),
+    adjacency entries 16 each, located site again 32, list entries 24 each
+    (bounding sphere 16 + triangle slot and ell 8), triangle records 48 per
+    exact test, the winner's record 48 + user id 4, outputs 20."""
+    per = (12 + 4 + 4 + 32 * ctr["walk_steps"] / n + 16 * ctr["adj_read"] / n + 32
+           + 24 * ctr["list_read"] / n + 48 * ctr["exact_tests"] / n + 52 + 20)
+    return per
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--points", type=int, default=10_000_000, help="total points (half uniform, half near-surface)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward timings")
+    ap.add_argument("--cpu-sample", type=int, default=4000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the query path shards "
+              "by replicating the mesh structure and splitting the points, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2605_00429_amd as p2m
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    log("generating workload")
+    n_half = args.points // 2
+    c = gen.config_c2(n_half, args.points - n_half)
+    V, F, Q, D = c["V"], c["F"], c["Q"], c["D"]
+    n = len(Q)
+    log(f"mesh {len(V)} vertices / {len(F)} triangles, {n} points; building search structure")
+    t0 = time.time()
+    mesh = p2m.Mesh(V, F)
+    build_s = time.time() - t0
+    st = mesh.stats()
+    log(f"build {build_s:.1f}s: {st['n_sites']} sites ({st['n_aux_sites']} auxiliary), "
+        f"lists avg {st['list_avg']:.1f} max {st['list_max']}, adjacency avg {st['adj_avg']:.1f}")
+
+    q = torch.from_numpy(Q).to(dev)
+    stream = torch.cuda.current_stream()
+
+    # algorithmic bytes from the instrumented forward (same results, untimed)
+    _, _, _, ctr = p2m.query_counters(mesh, q)
+    torch.cuda.synchronize()
+    bpq = bytes_per_query(ctr, n)
+    log(f"per query: walk steps {ctr['walk_steps'] / n:.2f}, adjacency read {ctr['adj_read'] / n:.1f}, "
+        f"list read {ctr['list_read'] / n:.1f} of {ctr['list_len'] / n:.1f}, exact tests "
+        f"{ctr['exact_tests'] / n:.2f}, fallback {ctr['fallback']}; {bpq:.0f} B/query")
+
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    out = (torch.empty(n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.int32, device=dev),
+           torch.empty((n, 3), dtype=torch.float32, device=dev))
+
+    def step():
+        p2m.lib().p2m_sort_points(mesh.handle, p2m._ptr(q), n, p2m._ptr(order), p2m._stream(stream))
+        ev_mid.record(stream)
+        p2m.query_ordered(mesh, q, order, out=out, stream=stream)
+
+    ev_mid = torch.cuda.Event(enable_timing=True)
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    mids = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        ev_mid = mids[k]
+        step()
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    step_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    sort_ms = [s.elapsed_time(m) for s, m in zip(starts, mids)]
+    search_ms = [m.elapsed_time(e) for m, e in zip(mids, ends)]
+    ms_per_step = sum(step_ms) / args.steps
+    search_avg = sum(search_ms) / args.steps
+    mqps = n / (ms_per_step * 1e-3) / 1e6
+    log(f"forward: {ms_per_step:.3f} ms/step (sort {sum(sort_ms) / args.steps:.3f}, search "
+        f"{search_avg:.3f}) = {mqps:.1f} Mq/s; wall {wall:.3f}s")
+
+    result = {
+        "metric": "Mqueries/s fwd and fwd+bwd, 327k-tri mesh, 10M pts; achieved HBM GB/s",
+        "value": round(mqps, 2),
+        "unit": "Mqueries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "displaced icosphere-7 (327,680 triangles, 163,842 vertices); "
+                        f"{n} points: {n_half} uniform in box x1.2 + {n - n_half} near-surface sigma 0.5% diag",
+            "n_points": n, "n_triangles": len(F), "locate_predicate": "f64",
+        },
+    }
+
+    kh = kernel_source_hash()
+    alg_bytes = bpq * n
+    achieved = alg_bytes / (search_avg * 1e-3) / 1e9
+    traffic = load_traffic(kh, n)
+    result["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": "fwd_kernel (search: locate + list scan)", "kernel_ms": round(search_avg, 4),
+        "bytes_per_query": round(bpq, 1), "kernel_hash": kh,
+    }
+    result["sort_ms"] = round(sum(sort_ms) / args.steps, 4)
+    result["per_query"] = {k: round(v / n, 3) for k, v in ctr.items()}
+    result["structure"] = {k: st[k] for k in ("n_sites", "n_aux_sites", "list_avg", "list_max", "adj_avg",
+                                              "list_nnz", "device_bytes")}
+    result["build_s"] = round(build_s, 2)
+
+    if not args.no_grad:
+        g = torch.from_numpy(np.random.default_rng(2605_00429 + 3).normal(size=n).astype(np.float32)).to(dev)
+        gv = torch.zeros((len(V), 3), dtype=torch.float32, device=dev)
+        gq = torch.empty((n, 3), dtype=torch.float32, device=dev)
+
+        def fwd_bwd():
+            gv.zero_()
+            d, t, cl = p2m.query(mesh, q, stream=stream)
+            p2m.lib().p2m_query_backward(mesh.handle, p2m._ptr(q), n, p2m._ptr(t), None, None, p2m._ptr(g),
+                                         p2m._ptr(gq), p2m._ptr(gv), p2m._stream(stream))
+
+        def fused():
+            gv.zero_()
+            p2m.lib().p2m_query_fused(mesh.handle, p2m._ptr(q), n, p2m._ptr(g), p2m._ptr(out[0]),
+                                      p2m._ptr(out[1]), p2m._ptr(out[2]), p2m._ptr(gq), p2m._ptr(gv),
+                                      p2m._stream(stream))
+
+        for name, fn in (("fwd_bwd", fwd_bwd), ("fused", fused)):
+            for _ in range(max(1, args.warmup)):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            result[f"{name}_mqps"] = round(n / (ms * 1e-3) / 1e6, 2)
+            result[f"{name}_ms"] = round(ms, 4)
+            log(f"{name}: {ms:.3f} ms/step = {result[f'{name}_mqps']:.1f} Mq/s")
+
+    if not args.no_cpu_baseline:
+        import oracle
+        k = max(2, args.cpu_sample)
+        idx = np.concatenate([np.arange(k // 2), n_half + np.arange(k - k // 2)])
+        Qs = np.ascontiguousarray(Q[idx])
+        log(f"oracle on {len(Qs)} sampled points (brute force over {len(F)} triangles)")
+        t0 = time.perf_counter()
+        d64, t64, _, used = oracle.distance(V, F, Qs, want_closest=False)
+        cpu_s = time.perf_counter() - t0
+        d_gpu = out[0][torch.from_numpy(idx).to(dev)].cpu().numpy()
+        err = np.abs(d_gpu.astype(np.float64) - d64) / D
+        result["cpu_baseline"] = {
+            "value": round(len(Qs) / cpu_s / 1e6, 6), "unit": "Mqueries/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"{len(Qs)} points ({k // 2} uniform + {k - k // 2} near-surface, the first of each "
+                      f"half of the workload), FP64 brute force over all {len(F)} triangles, {cpu_s:.1f}s",
+        }
+        result["max_abs_err_over_diag"] = float(err.max())
+        log(f"oracle {cpu_s:.1f}s on {used} threads; GPU max |d - d64| / D = {err.max():.2e}")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * p2m.h - C ABI of the MI355X (gfx950) P2M++ point-to-mesh distance library.
+ *
+ * The method (P2M++, Sec. 3): partition space by the Voronoi diagram of a
+ * site set (the mesh vertices plus auxiliary sites placed where Voronoi
+ * vertices cluster, Sec. 3.2), precompute for every site an interception
+ * list of the triangles that can be closer to some point of its cell than
+ * the site's reference point (Sec. 3.3, Eq. (2), the Vertex Sphere Union
+ * theorem Eq. (3) and the conservative sphere Eq. (8)), and answer a query
+ * by locating the nearest site and taking the minimum exact point-triangle
+ * distance over its list with bounding-sphere pruning (Sec. 3.4).
+ *
+ * Conventions for every call below:
+ *   - Return value: P2M_OK (0) or one of the P2M_ERR_* codes;
+ *     p2m_last_error() gives a thread-local message for the last failure.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the device current when the handle was built.
+ *   - Arrays of points are row-major float32 x, y, z triples.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Query calls only enqueue work; they do not synchronise.  Errors of
+ *     asynchronous kernels surface at the caller's next synchronisation.
+ *   - n == 0 is a valid no-op.
+ */
+#ifndef P2M_H
+#define P2M_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    P2M_OK = 0,
+    P2M_ERR_INVALID_ARG = 1, /* null required pointer, negative size, bad option */
+    P2M_ERR_BAD_MESH = 2,    /* no triangles, index out of range, non-finite vertex */
+    P2M_ERR_OOM = 3,         /* host or device allocation failed, or a size limit hit */
+    P2M_ERR_HIP = 4,         /* HIP runtime or launch error (see p2m_last_error) */
+    P2M_ERR_INTERNAL = 5,    /* invariant violated inside the library */
+    P2M_ERR_NO_DEVICE = 6    /* handle built host-only (device = -1): no query calls */
+};
+
+typedef struct p2m_handle_* p2m_handle;
+typedef struct p2m_batch_* p2m_batch;
+
+/* A triangle mesh, in host memory.  vertices: n_vertices x 3 float32;
+ * triangles: n_triangles x 3 int32 0-based vertex indices.  p2m_build copies
+ * both; the caller may free them on return. */
+typedef struct {
+    const float* vertices;
+    int64_t n_vertices;
+    const int32_t* triangles;
+    int64_t n_triangles;
+} p2m_mesh_desc;
+
+/* Preprocessing options.  p2m_default_opts() fills the defaults below.
+ * The augmentation constants are the ones the paper leaves to experiment
+ * (Sec. 3.2, "Choice of Parameters"); none of them affects exactness. */
+typedef struct {
+    float domain_scale;        /* cells are clipped to the mesh box scaled by this about its
+                                  centre (default 10, the query region of Sec. 4); queries
+                                  outside it take an exact BVH fallback */
+    int32_t augment;           /* 1: ring-based auxiliary sites (Sec. 3.2), 0: vertex sites only */
+    float tau_scale;           /* density grid cell tau = tau_scale * mean edge length (2) */
+    int32_t dense_min_sites;   /* a grid cell is dense when at least max(this, dense_rel *
+                                  median) distinct sites have a Voronoi vertex in it; the
+                                  median is over grid cells holding mesh vertices (256) */
+    float dense_rel;           /* (8) */
+    int32_t ring_sites;        /* auxiliary sites on the enclosing sphere: 12 (icosahedron) */
+    int32_t aux_list_mode;     /* 0: one conservative sphere per auxiliary site, Eq. (8);
+                                  1: corner balls about the site's projection on the mesh
+                                  (Eq. (3) with that reference point; a subset of mode 0) (1) */
+    float list_inflation_rel;  /* corner-ball radius inflation / mesh box diagonal (1e-7) */
+    float seed_cell_scale;     /* seed grid cell = this * mean edge length (2) */
+    int64_t seed_max_cells;    /* cap on seed grid cells (16M) */
+    int32_t n_threads;         /* host preprocessing threads, 0 = all */
+    int32_t device;            /* HIP device to upload to; -2 (default) = the current
+                                  device; -1 = host only (inspection, no query calls) */
+} p2m_build_opts;
+
+/* Statistics of a built handle (list lengths as in Table 1 of the paper). */
+typedef struct {
+    int64_t n_vertices, n_triangles;
+    int64_t n_sites, n_vertex_sites, n_aux_sites, n_dense_cells;
+    int64_t adj_nnz, adj_max;
+    int64_t list_nnz, list_max;
+    double adj_avg, list_avg;
+    int32_t seed_dims[3];
+    double t_voronoi_s, t_optimize_s, t_lists_s, t_layout_s, t_total_s;
+    int64_t device_bytes;
+    double diag;
+} p2m_stats;
+
+/* Per-handle launch configuration of the query kernels. */
+typedef struct {
+    int32_t block_size; /* threads per block: 64..1024, multiple of 64 (default 256) */
+    int32_t reorder;    /* 1: sort queries by seed cell before the search (default 1) */
+} p2m_query_config;
+
+void p2m_default_opts(p2m_build_opts* opts);
+
+/* Preprocess a mesh (Sec. 3.2-3.3) and upload the search structure.
+ * Synchronous; runs on host threads.  opts may be NULL (defaults).
+ * Unreferenced vertices are not sites; vertices at equal positions share one
+ * site.  On success *out owns all host and device memory of the structure. */
+int32_t p2m_build(const p2m_mesh_desc* mesh, const p2m_build_opts* opts, p2m_handle* out);
+
+/* Free a handle.  The caller must first synchronise streams that used it. */
+int32_t p2m_destroy(p2m_handle h);
+
+/* Distance query (Sec. 3.4): for each point, locate the nearest site, then
+ * the minimum exact point-triangle distance over its interception list.
+ *   d_points:      device, n x 3 float32
+ *   d_out_dist:    device, n float32 (required); NaN for a non-finite point
+ *   d_out_tri:     device, n int32 (nullable); caller's triangle id, -1 for NaN
+ *   d_out_closest: device, n x 3 float32 (nullable); closest point on the mesh
+ * Calls sharing one handle must not run concurrently on different streams
+ * (the handle's query workspace is reused). */
+int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
+                  int32_t* d_out_tri, float* d_out_closest, void* stream);
+
+/* The two halves of p2m_query, for callers that sort once and query several
+ * times (or time the search kernel alone).
+ * p2m_sort_points: writes to d_order (device, n int32) the order in which
+ *   p2m_query visits the points: sorted by the Morton rank of each point's
+ *   seed-grid cell, points outside the domain box last.  Uses the handle's
+ *   workspace (same concurrency rule as p2m_query).
+ * p2m_query_ordered: the search of p2m_query, visiting point d_order[j] at
+ *   thread j (d_order a permutation of 0..n-1, or NULL for 0..n-1); outputs
+ *   are indexed like d_points. */
+int32_t p2m_sort_points(p2m_handle h, const float* d_points, int64_t n, int32_t* d_order,
+                        void* stream);
+int32_t p2m_query_ordered(p2m_handle h, const float* d_points, const int32_t* d_order, int64_t n,
+                          float* d_out_dist, int32_t* d_out_tri, float* d_out_closest,
+                          void* stream);
+
+/* Gradient of L = sum_i g_i d_i (not in the paper; envelope theorem):
+ *   dL/dq_i = g_i (q_i - p_i) / d_i;
+ *   dL/dv_k += -g_i lambda_k (q_i - p_i) / d_i for the 3 vertices of tri_i,
+ * with lambda the barycentrics of the closest point p_i; 0 when d_i = 0.
+ *   d_tri, d_closest, d_dist: the forward outputs for the same points
+ *   d_grad_dist:     device, n float32
+ *   d_grad_points:   device, n x 3 float32 (nullable), overwritten
+ *   d_grad_vertices: device, n_vertices x 3 float32 (nullable), accumulated
+ *                    with float32 atomics (caller zeroes it) */
+int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n,
+                           const int32_t* d_tri, const float* d_closest, const float* d_dist,
+                           const float* d_grad_dist, float* d_grad_points,
+                           float* d_grad_vertices, void* stream);
+
+/* Forward and backward in one pass when dL/dd is known up front.  Outputs as
+ * in p2m_query and p2m_query_backward (d_out_tri and d_out_closest nullable). */
+int32_t p2m_query_fused(p2m_handle h, const float* d_points, int64_t n,
+                        const float* d_grad_dist, float* d_out_dist, int32_t* d_out_tri,
+                        float* d_out_closest, float* d_grad_points, float* d_grad_vertices,
+                        void* stream);
+
+int32_t p2m_get_stats(p2m_handle h, p2m_stats* out);
+int32_t p2m_get_query_config(p2m_handle h, p2m_query_config* out);
+int32_t p2m_set_query_config(p2m_handle h, const p2m_query_config* cfg);
+
+/* Instrumented forward (same results as p2m_query) that also accumulates,
+ * into d_counters (device, 6 uint64, caller-zeroed): walk steps, adjacency
+ * entries read, list entries read, exact point-triangle tests, queries
+ * answered by the fallback, sum of the located site's list length. */
+int32_t p2m_query_counters(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
+                           int32_t* d_out_tri, float* d_out_closest,
+                           unsigned long long* d_counters, void* stream);
+
+/* Host-side inspection of the built structure (no GPU needed).
+ * p2m_host_sites: n_sites x 3 float32 positions and is-auxiliary flags
+ *   (either pointer nullable); sites in device order.
+ * p2m_host_site_of_vertex: n_vertices int32 site id per caller vertex (-1 if
+ *   unreferenced).
+ * p2m_host_list: caller triangle ids of site `site`'s list (in scan order);
+ *   writes min(len, cap) ids and the full length to *len.
+ * p2m_host_neighbors: Delaunay neighbours of `site` used by the locate walk.
+ * p2m_host_locate: nearest site of each host point as the device walk finds
+ *   it (a host replay of the walk, for testing). */
+int32_t p2m_host_sites(p2m_handle h, float* out_xyz, uint8_t* out_is_aux);
+int32_t p2m_host_site_of_vertex(p2m_handle h, int32_t* out);
+int32_t p2m_host_list(p2m_handle h, int64_t site, int32_t* out_tris, int64_t cap, int64_t* len);
+int32_t p2m_host_neighbors(p2m_handle h, int64_t site, int32_t* out, int64_t cap, int64_t* len);
+int32_t p2m_host_locate(p2m_handle h, const float* points, int64_t n, int32_t* out_site);
+
+/* Batched form (not in the paper): many meshes and query sets of uneven
+ * sizes in one persistent launch, captured in a HIP graph.
+ *   p2m_batch_create: meshes[n_meshes] (handles outlive the batch),
+ *     h_query_counts[n_meshes] (host); autotune = 1 times candidate tile and
+ *     grid sizes on the first bind; cache_path (nullable) keeps the choice.
+ *   p2m_batch_bind: device buffers for the concatenated queries of all
+ *     meshes (mesh i's points follow mesh i-1's), outputs laid out the same
+ *     way; d_grad_dist nullable (forward only), else d_grad_vertices[i] is
+ *     mesh i's n_vertices x 3 accumulator (device, caller-zeroed, entries
+ *     nullable) and d_grad_points (nullable) is n_total x 3.  Captures the
+ *     graph on `stream`.
+ *   p2m_batch_launch: replays the graph on `stream`. */
+int32_t p2m_batch_create(const p2m_handle* meshes, int32_t n_meshes, const int64_t* h_query_counts,
+                         int32_t autotune, const char* cache_path, p2m_batch* out);
+int32_t p2m_batch_bind(p2m_batch b, const float* d_points, float* d_out_dist, int32_t* d_out_tri,
+                       float* d_out_closest, const float* d_grad_dist, float* d_grad_points,
+                       float* const* d_grad_vertices, void* stream);
+int32_t p2m_batch_launch(p2m_batch b, void* stream);
+/* Chosen tile size (queries per work item) and persistent grid size. */
+int32_t p2m_batch_config(p2m_batch b, int32_t* tile, int32_t* grid, int32_t* block);
+int32_t p2m_batch_destroy(p2m_batch b);
+
+const char* p2m_status_string(int32_t status);
+const char* p2m_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P2M_H */

@@ -1,0 +1,349 @@
+"""MI355X-native P2M++ point-to-mesh distance queries.
+
+``Mesh(V, F)`` runs the host preprocessing (site augmentation, Voronoi cells,
+interception lists) and uploads the search structure; ``distance(mesh, pts)``
+answers queries on the GPU with hand-written HIP kernels and is
+differentiable with respect to the points and the mesh vertices.
+
+Every call goes through the C ABI of ``libp2m.so`` (``include/p2m.h``); this
+module only marshals arguments.  PyTorch supplies device memory and streams.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import P2MError, check, lib
+
+__all__ = ["Mesh", "Batch", "distance", "query", "query_backward", "query_fused",
+           "query_counters", "sort_points", "query_ordered", "P2MError", "build_opts"]
+
+
+def build_opts(**kw):
+    """A ``p2m_build_opts`` with the library defaults, overridden by ``kw``."""
+    o = _lib.default_opts()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown build option {k!r}")
+        setattr(o, k, v)
+    return o
+
+
+def _np_mesh(V, F):
+    try:
+        import torch
+        if isinstance(V, torch.Tensor):
+            V = V.detach().cpu().numpy()
+        if isinstance(F, torch.Tensor):
+            F = F.detach().cpu().numpy()
+    except ImportError:
+        pass
+    V = np.ascontiguousarray(V, dtype=np.float32).reshape(-1, 3)
+    F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
+    return V, F
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Mesh:
+    """A triangle mesh preprocessed for P2M++ queries.
+
+    ``device``: a CUDA/HIP device (index or ``torch.device``) to upload to,
+    ``"host"`` for a host-only build (inspection, no queries), or ``None``
+    for torch's current device.  Extra keyword arguments set
+    ``p2m_build_opts`` fields.
+    """
+
+    def __init__(self, V, F, device=None, **opts):
+        V_np, F_np = _np_mesh(V, F)
+        self.V = V_np
+        self.F = F_np
+        self.vertices = V if not isinstance(V, np.ndarray) else None  # torch tensor for autograd
+        o = build_opts(**opts)
+        if device == "host":
+            o.device = -1
+            self.device = None
+        else:
+            import torch
+            if device is None:
+                dev = torch.cuda.current_device()
+            else:
+                dev = torch.device(device).index if not isinstance(device, int) else device
+                if dev is None:
+                    dev = torch.cuda.current_device()
+            o.device = int(dev)
+            self.device = torch.device("cuda", int(dev))
+        desc = _lib.p2m_mesh_desc(V_np.ctypes.data_as(ctypes.c_void_p), len(V_np),
+                                  F_np.ctypes.data_as(ctypes.c_void_p), len(F_np))
+        h = ctypes.c_void_p()
+        check(lib().p2m_build(ctypes.byref(desc), ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self.opts = o
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().p2m_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ inspection
+    def stats(self):
+        s = _lib.p2m_stats()
+        check(lib().p2m_get_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    @property
+    def n_sites(self):
+        return self.stats()["n_sites"]
+
+    def query_config(self):
+        c = _lib.p2m_query_config()
+        check(lib().p2m_get_query_config(self.handle, ctypes.byref(c)))
+        return {"block_size": c.block_size, "reorder": c.reorder}
+
+    def set_query_config(self, block_size=None, reorder=None):
+        cur = self.query_config()
+        c = _lib.p2m_query_config(block_size if block_size is not None else cur["block_size"],
+                                  int(reorder) if reorder is not None else cur["reorder"])
+        check(lib().p2m_set_query_config(self.handle, ctypes.byref(c)))
+
+    def host_sites(self):
+        n = self.n_sites
+        xyz = np.empty((n, 3), np.float32)
+        aux = np.empty(n, np.uint8)
+        check(lib().p2m_host_sites(self.handle, xyz.ctypes.data_as(ctypes.c_void_p),
+                                   aux.ctypes.data_as(ctypes.c_void_p)))
+        return xyz, aux.astype(bool)
+
+    def site_of_vertex(self):
+        out = np.empty(len(self.V), np.int32)
+        check(lib().p2m_host_site_of_vertex(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def host_list(self, site):
+        n = ctypes.c_int64()
+        check(lib().p2m_host_list(self.handle, int(site), None, 0, ctypes.byref(n)))
+        out = np.empty(n.value, np.int32)
+        check(lib().p2m_host_list(self.handle, int(site), out.ctypes.data_as(ctypes.c_void_p),
+                                  n.value, ctypes.byref(n)))
+        return out
+
+    def host_neighbors(self, site):
+        n = ctypes.c_int64()
+        check(lib().p2m_host_neighbors(self.handle, int(site), None, 0, ctypes.byref(n)))
+        out = np.empty(n.value, np.int32)
+        check(lib().p2m_host_neighbors(self.handle, int(site), out.ctypes.data_as(ctypes.c_void_p),
+                                       n.value, ctypes.byref(n)))
+        return out
+
+    def host_locate(self, P):
+        P = np.ascontiguousarray(P, np.float32).reshape(-1, 3)
+        out = np.empty(len(P), np.int32)
+        check(lib().p2m_host_locate(self.handle, P.ctypes.data_as(ctypes.c_void_p), len(P),
+                                    out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def list_lengths(self):
+        n = self.n_sites
+        out = np.empty(n, np.int64)
+        L = ctypes.c_int64()
+        for s in range(n):
+            check(lib().p2m_host_list(self.handle, s, None, 0, ctypes.byref(L)))
+            out[s] = L.value
+        return out
+
+
+def _check_points(mesh, points):
+    import torch
+    if mesh.device is None:
+        raise P2MError(_lib.P2M_ERR_NO_DEVICE, "mesh was built host-only")
+    if not isinstance(points, torch.Tensor) or points.device != mesh.device:
+        raise ValueError(f"points must be a tensor on {mesh.device}")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be an (n, 3) float32 tensor")
+    return points.contiguous()
+
+
+def query(mesh, points, want_tri=True, want_closest=True, stream=None):
+    """Forward query: ``(dist, tri, closest)`` (tri / closest may be None)."""
+    import torch
+    p = _check_points(mesh, points)
+    n = p.shape[0]
+    dist = torch.empty(n, dtype=torch.float32, device=p.device)
+    tri = torch.empty(n, dtype=torch.int32, device=p.device) if want_tri else None
+    closest = torch.empty((n, 3), dtype=torch.float32, device=p.device) if want_closest else None
+    check(lib().p2m_query(mesh.handle, _ptr(p), n, _ptr(dist), _ptr(tri), _ptr(closest), _stream(stream)))
+    return dist, tri, closest
+
+
+def sort_points(mesh, points, stream=None):
+    """The order (int32 permutation) in which ``query`` visits the points."""
+    import torch
+    p = _check_points(mesh, points)
+    order = torch.empty(p.shape[0], dtype=torch.int32, device=p.device)
+    check(lib().p2m_sort_points(mesh.handle, _ptr(p), p.shape[0], _ptr(order), _stream(stream)))
+    return order
+
+
+def query_ordered(mesh, points, order, out=None, stream=None):
+    """The search half of ``query`` with a given visiting order (or None).
+    ``out`` may supply preallocated ``(dist, tri, closest)`` tensors."""
+    import torch
+    p = _check_points(mesh, points)
+    n = p.shape[0]
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float32, device=p.device),
+               torch.empty(n, dtype=torch.int32, device=p.device),
+               torch.empty((n, 3), dtype=torch.float32, device=p.device))
+    dist, tri, closest = out
+    check(lib().p2m_query_ordered(mesh.handle, _ptr(p), _ptr(order), n, _ptr(dist), _ptr(tri),
+                                  _ptr(closest), _stream(stream)))
+    return dist, tri, closest
+
+
+def query_counters(mesh, points, stream=None):
+    """Instrumented forward: ``(dist, tri, closest, counters)`` with counters a
+    dict of totals over the points."""
+    import torch
+    p = _check_points(mesh, points)
+    n = p.shape[0]
+    dist = torch.empty(n, dtype=torch.float32, device=p.device)
+    tri = torch.empty(n, dtype=torch.int32, device=p.device)
+    closest = torch.empty((n, 3), dtype=torch.float32, device=p.device)
+    ctr = torch.zeros(8, dtype=torch.int64, device=p.device)
+    check(lib().p2m_query_counters(mesh.handle, _ptr(p), n, _ptr(dist), _ptr(tri), _ptr(closest),
+                                   _ptr(ctr), _stream(stream)))
+    c = ctr.cpu().tolist()
+    names = ["walk_steps", "adj_read", "list_read", "exact_tests", "fallback", "list_len"]
+    return dist, tri, closest, dict(zip(names, c))
+
+
+def query_backward(mesh, points, tri, grad_dist, grad_points=True, grad_vertices=None, stream=None):
+    """Gradients of ``sum(grad_dist * dist)``: ``(dL/dpoints, dL/dV)``.
+    ``grad_vertices`` may be a zeroed (nV, 3) tensor to accumulate into."""
+    import torch
+    p = _check_points(mesh, points)
+    n = p.shape[0]
+    g = grad_dist.contiguous().to(torch.float32)
+    gq = torch.empty((n, 3), dtype=torch.float32, device=p.device) if grad_points else None
+    check(lib().p2m_query_backward(mesh.handle, _ptr(p), n, _ptr(tri.contiguous()), None, None, _ptr(g),
+                                   _ptr(gq), _ptr(grad_vertices), _stream(stream)))
+    return gq, grad_vertices
+
+
+def query_fused(mesh, points, grad_dist, grad_vertices=None, stream=None):
+    """Forward and gradient in one pass: ``(dist, tri, closest, dL/dpoints)``;
+    dL/dV is accumulated into ``grad_vertices`` when given."""
+    import torch
+    p = _check_points(mesh, points)
+    n = p.shape[0]
+    g = grad_dist.contiguous().to(torch.float32)
+    dist = torch.empty(n, dtype=torch.float32, device=p.device)
+    tri = torch.empty(n, dtype=torch.int32, device=p.device)
+    closest = torch.empty((n, 3), dtype=torch.float32, device=p.device)
+    gq = torch.empty((n, 3), dtype=torch.float32, device=p.device)
+    check(lib().p2m_query_fused(mesh.handle, _ptr(p), n, _ptr(g), _ptr(dist), _ptr(tri), _ptr(closest),
+                                _ptr(gq), _ptr(grad_vertices), _stream(stream)))
+    return dist, tri, closest, gq
+
+
+def _make_fn():
+    import torch
+
+    class _P2MDistance(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, points, vertices, mesh):
+            dist, tri, closest = query(mesh, points.detach())
+            ctx.mesh = mesh
+            ctx.save_for_backward(points.detach(), tri)
+            ctx.has_vertices = vertices is not None
+            ctx.mark_non_differentiable(tri, closest)
+            return dist, tri, closest
+
+        @staticmethod
+        def backward(ctx, g_dist, g_tri, g_closest):
+            points, tri = ctx.saved_tensors
+            mesh = ctx.mesh
+            need_p = ctx.needs_input_grad[0]
+            need_v = ctx.has_vertices and ctx.needs_input_grad[1]
+            if g_dist is None or not (need_p or need_v):
+                return None, None, None
+            gv = torch.zeros((len(mesh.V), 3), dtype=torch.float32, device=points.device) if need_v else None
+            gq, gv = query_backward(mesh, points, tri, g_dist, grad_points=need_p, grad_vertices=gv)
+            return gq, gv, None
+
+    return _P2MDistance
+
+
+_FN = None
+
+
+def distance(mesh, points):
+    """Differentiable distance: ``(dist, tri, closest)``.  Gradients flow to
+    ``points`` and, if the mesh was built from a tensor that requires grad,
+    to those vertices (the distance at the built positions)."""
+    global _FN
+    if _FN is None:
+        _FN = _make_fn()
+    v = mesh.vertices
+    import torch
+    if not (isinstance(v, torch.Tensor) and v.requires_grad):
+        v = None
+    return _FN.apply(points, v, mesh)
+
+
+class Batch:
+    """Many meshes and query sets in one persistent, graph-captured launch."""
+
+    def __init__(self, meshes, counts, autotune=True, cache_path=None):
+        self.meshes = list(meshes)
+        self.counts = [int(c) for c in counts]
+        arr = (ctypes.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        cnt = (ctypes.c_int64 * len(self.counts))(*self.counts)
+        h = ctypes.c_void_p()
+        check(lib().p2m_batch_create(arr, len(self.meshes), cnt, int(bool(autotune)),
+                                     cache_path.encode() if cache_path else None, ctypes.byref(h)))
+        self.handle = h
+        self._keep = None
+
+    def bind(self, points, dist, tri=None, closest=None, grad_dist=None, grad_points=None,
+             grad_vertices=None, stream=None):
+        gv = None
+        if grad_vertices is not None:
+            gv = (ctypes.c_void_p * len(self.meshes))(*[t.data_ptr() if t is not None else 0
+                                                        for t in grad_vertices])
+        self._keep = (points, dist, tri, closest, grad_dist, grad_points, grad_vertices)
+        check(lib().p2m_batch_bind(self.handle, _ptr(points), _ptr(dist), _ptr(tri), _ptr(closest),
+                                   _ptr(grad_dist), _ptr(grad_points), gv, _stream(stream)))
+
+    def launch(self, stream=None):
+        check(lib().p2m_batch_launch(self.handle, _stream(stream)))
+
+    def config(self):
+        t, g, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().p2m_batch_config(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(b)))
+        return {"tile": t.value, "grid": g.value, "block": b.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().p2m_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,462 @@
+// C ABI of the library (declared in include/p2m.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "host/build.h"
+#include "p2m.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int32_t hip_fail(hipError_t e, const char* what)
+{
+    return fail(P2M_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Makes `dev` current for the scope and restores the caller's device.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct p2m_handle_ {
+    p2m::HostStructure H;
+    int device = -1;
+    p2m::DevMesh dm{};
+    std::vector<void*> allocs;
+    int64_t device_bytes = 0;
+    p2m_query_config cfg{256, 1};
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+
+    ~p2m_handle_()
+    {
+        if (device >= 0) {
+            DeviceGuard g(device);
+            for (void* p : allocs) (void)hipFree(p);
+            if (ws) (void)hipFree(ws);
+        }
+    }
+
+    template <typename T>
+    const T* upload(const void* src, size_t bytes)
+    {
+        void* p = nullptr;
+        const size_t nb = bytes ? bytes : 16;
+        hipError_t e = hipMalloc(&p, nb);
+        if (e != hipSuccess) throw p2m::Error(P2M_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(p);
+        device_bytes += (int64_t)nb;
+        if (bytes) {
+            e = hipMemcpy(p, src, bytes, hipMemcpyHostToDevice);
+            if (e != hipSuccess) throw p2m::Error(P2M_ERR_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+        return (const T*)p;
+    }
+
+    void upload_all()
+    {
+        using namespace p2m;
+        const HostStructure& h = H;
+        dm.site_xyz = upload<float4>(h.site_xyz.data(), h.site_xyz.size() * 4);
+        dm.site_rng = upload<int4>(h.site_rng.data(), h.site_rng.size() * 4);
+        dm.adj = upload<float4>(h.adj.data(), h.adj.size() * 4);
+        dm.list_sph = upload<float4>(h.list_sph.data(), h.list_sph.size() * 4);
+        dm.list_aux = upload<int2>(h.list_aux.data(), h.list_aux.size() * 4);
+        dm.tri_rec = upload<float4>(h.tri_rec.data(), h.tri_rec.size() * 4);
+        dm.tri_user = upload<int32_t>(h.tri_user.data(), h.tri_user.size() * 4);
+        dm.tri_vid = upload<int4>(h.tri_vid.data(), h.tri_vid.size() * 4);
+        std::vector<int32_t> slot(h.n_triangles);
+        for (int64_t i = 0; i < h.n_triangles; ++i) slot[h.tri_user[i]] = (int32_t)i;
+        dm.tri_slot = upload<int32_t>(slot.data(), slot.size() * 4);
+        dm.seed = upload<int32_t>(h.seed.data(), h.seed.size() * 4);
+        // Morton rank of every seed cell, for sorting queries
+        const int64_t nc = (int64_t)h.seed.size();
+        std::vector<std::pair<uint64_t, int32_t>> mk(nc);
+        auto spread = [](uint64_t x) {
+            x &= 0x1fffff;
+            x = (x | x << 32) & 0x1f00000000ffffULL;
+            x = (x | x << 16) & 0x1f0000ff0000ffULL;
+            x = (x | x << 8) & 0x100f00f00f00f00fULL;
+            x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+            x = (x | x << 2) & 0x1249249249249249ULL;
+            return x;
+        };
+        for (int64_t c = 0; c < nc; ++c) {
+            const int64_t ix = c % h.gdim[0], iy = (c / h.gdim[0]) % h.gdim[1], iz = c / ((int64_t)h.gdim[0] * h.gdim[1]);
+            mk[c] = {spread(ix) | (spread(iy) << 1) | (spread(iz) << 2), (int32_t)c};
+        }
+        std::sort(mk.begin(), mk.end());
+        std::vector<int32_t> rank(nc);
+        for (int64_t r = 0; r < nc; ++r) rank[mk[r].second] = (int32_t)r;
+        dm.cell_rank = upload<int32_t>(rank.data(), rank.size() * 4);
+        dm.bvh = upload<float4>(h.bvh.data(), h.bvh.size() * 4);
+        for (int k = 0; k < 3; ++k) {
+            dm.gdim[k] = h.gdim[k];
+            dm.gorg[k] = h.gorg[k];
+            dm.dlo[k] = h.dlo[k];
+            dm.dhi[k] = h.dhi[k];
+        }
+        dm.ginv = 1.0f / h.gcell;
+        dm.n_sites = h.n_sites;
+        dm.n_tris = (int32_t)h.n_triangles;
+        dm.n_vertices = (int32_t)h.n_vertices;
+        dm.n_cells = (int32_t)nc;
+    }
+
+    // Grows the query workspace; waits for earlier work on `st` first.
+    int32_t ensure_ws(size_t bytes, hipStream_t st)
+    {
+        if (ws_bytes >= bytes) return P2M_OK;
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        if (ws) (void)hipFree(ws);
+        ws = nullptr;
+        ws_bytes = 0;
+        const size_t nb = bytes + bytes / 4;
+        e = hipMalloc(&ws, nb);
+        if (e != hipSuccess) return fail(P2M_ERR_OOM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+        ws_bytes = nb;
+        return P2M_OK;
+    }
+};
+
+namespace p2m {
+const DevMesh& handle_devmesh(const p2m_handle_* h) { return h->dm; }
+int handle_device(const p2m_handle_* h) { return h->device; }
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace p2m
+
+extern "C" {
+
+void p2m_default_opts(p2m_build_opts* o)
+{
+    if (!o) return;
+    o->domain_scale = 10.0f;
+    o->augment = 1;
+    o->tau_scale = 2.0f;
+    o->dense_min_sites = 256;
+    o->dense_rel = 8.0f;
+    o->ring_sites = 12;
+    o->aux_list_mode = 1;
+    o->list_inflation_rel = 1e-7f;
+    o->seed_cell_scale = 2.0f;
+    o->seed_max_cells = 16 << 20;
+    o->n_threads = 0;
+    o->device = -2;
+}
+
+int32_t p2m_build(const p2m_mesh_desc* mesh, const p2m_build_opts* opts, p2m_handle* out)
+{
+    if (!mesh || !out) return fail(P2M_ERR_INVALID_ARG, "null mesh or output pointer");
+    *out = nullptr;
+    p2m_build_opts o;
+    p2m_default_opts(&o);
+    if (opts) o = *opts;
+    p2m_handle h = nullptr;
+    try {
+        h = new p2m_handle_();
+        p2m::build_host(*mesh, o, h->H);
+        int dev = o.device;
+        if (dev == -2) {
+            hipError_t e = hipGetDevice(&dev);
+            if (e != hipSuccess) {
+                delete h;
+                return hip_fail(e, "hipGetDevice");
+            }
+        }
+        if (dev >= 0) {
+            DeviceGuard g(dev);
+            if (!g.ok) {
+                delete h;
+                return fail(P2M_ERR_HIP, "cannot select HIP device " + std::to_string(dev));
+            }
+            h->device = dev;
+            h->upload_all();
+        }
+        h->H.stats.device_bytes = h->device_bytes;
+    } catch (const p2m::Error& e) {
+        delete h;
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc&) {
+        delete h;
+        return fail(P2M_ERR_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        delete h;
+        return fail(P2M_ERR_INTERNAL, e.what());
+    }
+    *out = h;
+    return P2M_OK;
+}
+
+int32_t p2m_destroy(p2m_handle h)
+{
+    delete h;
+    return P2M_OK;
+}
+
+int32_t p2m_get_stats(p2m_handle h, p2m_stats* out)
+{
+    if (!h || !out) return fail(P2M_ERR_INVALID_ARG, "null handle or output");
+    *out = h->H.stats;
+    return P2M_OK;
+}
+
+int32_t p2m_get_query_config(p2m_handle h, p2m_query_config* out)
+{
+    if (!h || !out) return fail(P2M_ERR_INVALID_ARG, "null handle or output");
+    *out = h->cfg;
+    return P2M_OK;
+}
+
+int32_t p2m_set_query_config(p2m_handle h, const p2m_query_config* c)
+{
+    if (!h || !c) return fail(P2M_ERR_INVALID_ARG, "null handle or config");
+    if (c->block_size < 64 || c->block_size > 1024 || c->block_size % 64 != 0)
+        return fail(P2M_ERR_INVALID_ARG, "block_size must be a multiple of 64 in [64, 1024]");
+    h->cfg = *c;
+    return P2M_OK;
+}
+
+static int32_t query_common(p2m_handle h, const float* q, int64_t n, float* dist, int32_t* tri, float* closest,
+                            const float* g, float* gq, float* gv, unsigned long long* ctr, bool fused,
+                            void* stream)
+{
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (n == 0) return P2M_OK;
+    if (!q || !dist) return fail(P2M_ERR_INVALID_ARG, "null points or distance output");
+    if (fused && !g) return fail(P2M_ERR_INVALID_ARG, "null upstream gradient");
+    if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
+    DeviceGuard dg(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    p2m::FwdArgs a{};
+    a.q = q;
+    a.n = n;
+    a.dist = dist;
+    a.tri = tri;
+    a.closest = closest;
+    a.grad_dist = g;
+    a.grad_q = gq;
+    a.grad_v = gv;
+    a.ctr = ctr;
+    if (h->cfg.reorder) {
+        const size_t need = p2m::reorder_workspace_bytes(n, h->dm.n_cells);
+        int32_t rc = h->ensure_ws(need, st);
+        if (rc != P2M_OK) return rc;
+        hipError_t e = p2m::launch_reorder(h->dm, q, n, h->ws, &a.perm, st);
+        if (e != hipSuccess) return hip_fail(e, "reorder launch");
+    }
+    hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, fused, ctr != nullptr, st);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return P2M_OK;
+}
+
+int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist, int32_t* d_out_tri,
+                  float* d_out_closest, void* stream)
+{
+    return query_common(h, d_points, n, d_out_dist, d_out_tri, d_out_closest, nullptr, nullptr, nullptr,
+                        nullptr, false, stream);
+}
+
+int32_t p2m_sort_points(p2m_handle h, const float* d_points, int64_t n, int32_t* d_order, void* stream)
+{
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (n == 0) return P2M_OK;
+    if (!d_points || !d_order) return fail(P2M_ERR_INVALID_ARG, "null points or order");
+    if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
+    DeviceGuard dg(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->dm.n_cells), st);
+    if (rc != P2M_OK) return rc;
+    const int32_t* perm = nullptr;
+    hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->ws, &perm, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_order, perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "sort launch");
+    return P2M_OK;
+}
+
+int32_t p2m_query_ordered(p2m_handle h, const float* d_points, const int32_t* d_order, int64_t n,
+                          float* d_out_dist, int32_t* d_out_tri, float* d_out_closest, void* stream)
+{
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (n == 0) return P2M_OK;
+    if (!d_points || !d_out_dist) return fail(P2M_ERR_INVALID_ARG, "null points or distance output");
+    if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
+    DeviceGuard dg(h->device);
+    p2m::FwdArgs a{};
+    a.q = d_points;
+    a.perm = d_order;
+    a.n = n;
+    a.dist = d_out_dist;
+    a.tri = d_out_tri;
+    a.closest = d_out_closest;
+    hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, false, false, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return P2M_OK;
+}
+
+int32_t p2m_query_counters(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
+                           int32_t* d_out_tri, float* d_out_closest, unsigned long long* d_counters,
+                           void* stream)
+{
+    if (!d_counters) return fail(P2M_ERR_INVALID_ARG, "null counters");
+    return query_common(h, d_points, n, d_out_dist, d_out_tri, d_out_closest, nullptr, nullptr, nullptr,
+                        d_counters, false, stream);
+}
+
+int32_t p2m_query_fused(p2m_handle h, const float* d_points, int64_t n, const float* d_grad_dist,
+                        float* d_out_dist, int32_t* d_out_tri, float* d_out_closest, float* d_grad_points,
+                        float* d_grad_vertices, void* stream)
+{
+    return query_common(h, d_points, n, d_out_dist, d_out_tri, d_out_closest, d_grad_dist, d_grad_points,
+                        d_grad_vertices, nullptr, true, stream);
+}
+
+int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n, const int32_t* d_tri,
+                           const float* d_closest, const float* d_dist, const float* d_grad_dist,
+                           float* d_grad_points, float* d_grad_vertices, void* stream)
+{
+    (void)d_closest;
+    (void)d_dist;
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (n == 0) return P2M_OK;
+    if (!d_points || !d_tri || !d_grad_dist) return fail(P2M_ERR_INVALID_ARG, "null points, triangles or gradient");
+    DeviceGuard dg(h->device);
+    hipError_t e = p2m::launch_backward(h->dm, d_points, n, d_tri, d_grad_dist, d_grad_points, d_grad_vertices,
+                                        h->cfg.block_size, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return P2M_OK;
+}
+
+// ------------------------------------------------------------ inspection
+
+int32_t p2m_host_sites(p2m_handle h, float* out_xyz, uint8_t* out_is_aux)
+{
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    for (int32_t s = 0; s < h->H.n_sites; ++s) {
+        if (out_xyz) std::memcpy(out_xyz + 3 * (int64_t)s, &h->H.site_xyz[4 * (int64_t)s], 12);
+        if (out_is_aux) out_is_aux[s] = h->H.site_is_aux[s];
+    }
+    return P2M_OK;
+}
+
+int32_t p2m_host_site_of_vertex(p2m_handle h, int32_t* out)
+{
+    if (!h || !out) return fail(P2M_ERR_INVALID_ARG, "null handle or output");
+    std::memcpy(out, h->H.site_of_vertex.data(), sizeof(int32_t) * h->H.site_of_vertex.size());
+    return P2M_OK;
+}
+
+int32_t p2m_host_list(p2m_handle h, int64_t site, int32_t* out_tris, int64_t cap, int64_t* len)
+{
+    if (!h || !len || cap < 0) return fail(P2M_ERR_INVALID_ARG, "null handle or length");
+    if (site < 0 || site >= h->H.n_sites) return fail(P2M_ERR_INVALID_ARG, "site out of range");
+    const int32_t b = h->H.site_rng[4 * site + 2], e = h->H.site_rng[4 * site + 3];
+    *len = e - b;
+    for (int64_t k = 0; k < std::min<int64_t>(cap, e - b) && out_tris; ++k)
+        out_tris[k] = h->H.tri_user[h->H.list_aux[2 * (b + k)]];
+    return P2M_OK;
+}
+
+int32_t p2m_host_neighbors(p2m_handle h, int64_t site, int32_t* out, int64_t cap, int64_t* len)
+{
+    if (!h || !len || cap < 0) return fail(P2M_ERR_INVALID_ARG, "null handle or length");
+    if (site < 0 || site >= h->H.n_sites) return fail(P2M_ERR_INVALID_ARG, "site out of range");
+    const int32_t b = h->H.site_rng[4 * site], e = h->H.site_rng[4 * site + 1];
+    *len = e - b;
+    for (int64_t k = 0; k < std::min<int64_t>(cap, e - b) && out; ++k) {
+        int32_t id;
+        std::memcpy(&id, &h->H.adj[4 * (b + k) + 3], 4);
+        out[k] = id;
+    }
+    return P2M_OK;
+}
+
+int32_t p2m_host_locate(p2m_handle h, const float* pts, int64_t n, int32_t* out_site)
+{
+    if (!h || (n > 0 && (!pts || !out_site))) return fail(P2M_ERR_INVALID_ARG, "null argument");
+    const p2m::HostStructure& H = h->H;
+    const float ginv = 1.0f / H.gcell;
+    for (int64_t i = 0; i < n; ++i) {
+        const float qx = pts[3 * i], qy = pts[3 * i + 1], qz = pts[3 * i + 2];
+        if (!std::isfinite(qx) || !std::isfinite(qy) || !std::isfinite(qz)) {
+            out_site[i] = -1;
+            continue;
+        }
+        auto cell = [&](float v, int k) {
+            const int c = (int)std::floor((v - H.gorg[k]) * ginv);
+            return std::min(std::max(c, 0), H.gdim[k] - 1);
+        };
+        int s = H.seed[((int64_t)cell(qz, 2) * H.gdim[1] + cell(qy, 1)) * H.gdim[0] + cell(qx, 0)];
+        for (int it = 0; it < 4096; ++it) {
+            const float* sp = &H.site_xyz[4 * (int64_t)s];
+            const double wx = (double)qx - sp[0], wy = (double)qy - sp[1], wz = (double)qz - sp[2];
+            double best = 0.0;
+            int nxt = -1;
+            for (int32_t k = H.site_rng[4 * (int64_t)s]; k < H.site_rng[4 * (int64_t)s + 1]; ++k) {
+                const float* a = &H.adj[4 * (int64_t)k];
+                const double dx = (double)a[0] - sp[0], dy = (double)a[1] - sp[1], dz = (double)a[2] - sp[2];
+                const double val = wx * dx + wy * dy + wz * dz - 0.5 * (dx * dx + dy * dy + dz * dz);
+                if (val > best) {
+                    best = val;
+                    std::memcpy(&nxt, &a[3], 4);
+                }
+            }
+            if (nxt < 0) break;
+            s = nxt;
+        }
+        out_site[i] = s;
+    }
+    return P2M_OK;
+}
+
+const char* p2m_status_string(int32_t s)
+{
+    switch (s) {
+    case P2M_OK: return "ok";
+    case P2M_ERR_INVALID_ARG: return "invalid argument";
+    case P2M_ERR_BAD_MESH: return "bad mesh";
+    case P2M_ERR_OOM: return "out of memory";
+    case P2M_ERR_HIP: return "HIP error";
+    case P2M_ERR_INTERNAL: return "internal error";
+    case P2M_ERR_NO_DEVICE: return "no device data";
+    default: return "unknown status";
+    }
+}
+
+const char* p2m_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Device-side layout of one built mesh and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace p2m {
+
+// Read-only search structure of one mesh in device memory (see build.h for
+// the meaning of each array).  Passed to kernels by value.
+struct DevMesh {
+    const float4* site_xyz;  // n_sites
+    const int4* site_rng;    // n_sites: adj begin, adj end, list begin, list end
+    const float4* adj;       // neighbour xyz + id bits
+    const float4* list_sph;  // bounding sphere per list entry
+    const int2* list_aux;    // triangle slot, ell bits
+    const float4* tri_rec;   // 3 per slot: (a, |e1|^2), (e1, e1.e2), (e2, |e2|^2)
+    const int32_t* tri_user; // slot -> caller triangle id
+    const int4* tri_vid;     // slot -> caller vertex ids
+    const int32_t* tri_slot; // caller triangle id -> slot
+    const int32_t* seed;     // seed grid (x fastest)
+    const int32_t* cell_rank;// seed cell -> rank in Morton order (query sorting)
+    const float4* bvh;       // 2 per node
+    int32_t gdim[3];
+    float gorg[3];
+    float ginv;              // 1 / seed cell size
+    float dlo[3], dhi[3];    // domain box
+    int32_t n_sites, n_tris, n_vertices, n_cells;
+};
+
+// Counter slots of the instrumented forward.
+enum { CTR_WALK_STEPS = 0, CTR_ADJ_READ, CTR_LIST_READ, CTR_EXACT, CTR_FALLBACK, CTR_LIST_LEN, CTR_N };
+
+struct FwdArgs {
+    const float* q;          // n x 3
+    const int32_t* perm;     // optional processing order
+    int64_t n;
+    float* dist;
+    int32_t* tri;            // nullable
+    float* closest;          // nullable
+    const float* grad_dist;  // fused only
+    float* grad_q;           // fused only, nullable
+    float* grad_v;           // fused only, nullable
+    unsigned long long* ctr; // counters only
+};
+
+// Arguments of the persistent batched kernel.  Queries of mesh i occupy
+// [q_off[i], q_off[i+1]) of the concatenated arrays; work item t covers
+// sorted positions [item_first[t], item_first[t] + tile) of mesh item_mesh[t].
+struct BatchArgs {
+    const float* q;
+    float* dist;
+    int32_t* tri;
+    float* closest;
+    const float* grad_dist;
+    float* grad_q;
+    float* const* grad_v;        // per mesh (device array of device pointers)
+    const int32_t* const* perm;  // per mesh, or null entries
+    const int64_t* q_off;        // n_meshes + 1
+    const int32_t* item_mesh;
+    const int64_t* item_first;
+    int32_t n_items;
+    int32_t tile;
+    unsigned* counter;
+};
+
+hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int block, bool fused,
+                        hipStream_t st);
+hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fused, bool counters,
+                          hipStream_t st);
+hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* tri,
+                           const float* g, float* grad_q, float* grad_v, int block, hipStream_t st);
+// Counting sort of queries by seed cell (Morton rank).  ws must hold
+// workspace_bytes(n, n_cells) bytes; writes the order to *perm_out.
+size_t reorder_workspace_bytes(int64_t n, int32_t n_cells);
+hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, void* ws, const int32_t** perm_out,
+                          hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+
+}  // namespace p2m

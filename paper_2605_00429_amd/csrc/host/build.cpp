@@ -1,0 +1,731 @@
+// P2M++ preprocessing (Sec. 3.2 and 3.3 of the paper), host side.
+//
+//  1. Sites: the referenced mesh vertices (one site per distinct position).
+//  2. Voronoi cells: each site's cell inside the domain box, by clipping the
+//     box with bisector half-spaces (kNN candidates first, then exact
+//     "is a site closer than s to this corner" checks until every corner
+//     is final).  The planes that bound a face are the site's Delaunay
+//     neighbours, used by the locate walk.
+//  3. Ring-based augmentation (Sec. 3.2): a uniform grid of scale tau counts
+//     Voronoi vertices; a dense grid cell gets a central site at the
+//     cluster's centroid plus sites on an enclosing sphere; sites that come
+//     too close to an accepted one are dropped (the overlap rule), and so is
+//     any auxiliary site whose cell would reach the domain box.
+//  4. Interception lists (Sec. 3.3): for an on-surface site v, every
+//     triangle meeting the union of the balls B(u, |u - v|) over the cell
+//     corners u (the Vertex Sphere Union theorem, Eq. (3)); for an auxiliary
+//     site s, reference point proj(s, M), either the single conservative
+//     sphere of Eq. (8) or the same corner-ball union about proj(s, M).
+//     Radii are inflated by delta so that rounding never loses a triangle.
+//  5. Per-triangle bounding spheres (Sec. 3.4, pruning) and, per list entry,
+//     ell = |s - c| - r, by which each list is sorted so that the query can
+//     stop once ell - |q - s| >= d_min (triangle inequality).
+//  6. Device layout: triangles in BVH leaf order, sites in Morton order,
+//     seed grid of exact nearest sites for the locate walk's start.
+#include "build.h"
+
+#include <chrono>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <unordered_map>
+
+#include "bvh.h"
+#include "cell.h"
+#include "kdtree.h"
+
+namespace p2m {
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+double secs_since(clk::time_point a) { return std::chrono::duration<double>(clk::now() - a).count(); }
+
+float round_down(double x)
+{
+    float f = (float)x;
+    if ((double)f > x) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+
+float round_up(double x)
+{
+    float f = (float)x;
+    if ((double)f < x) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+int32_t fbits(float f)
+{
+    int32_t i;
+    std::memcpy(&i, &f, 4);
+    return i;
+}
+
+float ibits(int32_t i)
+{
+    float f;
+    std::memcpy(&f, &i, 4);
+    return f;
+}
+
+uint64_t spread21(uint64_t x)
+{
+    x &= 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+
+uint64_t morton_of(d3 p, d3 lo, double inv)
+{
+    auto q = [&](double v, double l) {
+        double t = (v - l) * inv;
+        t = std::min(std::max(t, 0.0), 2097151.0);
+        return (uint64_t)t;
+    };
+    return spread21(q(p.x, lo.x)) | (spread21(q(p.y, lo.y)) << 1) | (spread21(q(p.z, lo.z)) << 2);
+}
+
+// Smallest sphere containing triangle (a, b, c): centre of the longest edge
+// for a right or obtuse (or degenerate) triangle, else the circumcentre.
+d3 min_sphere_center(d3 a, d3 b, d3 c)
+{
+    const double ab = norm2(b - a), bc = norm2(c - b), ca = norm2(a - c);
+    if (ab >= bc + ca) return (a + b) * 0.5;
+    if (bc >= ab + ca) return (b + c) * 0.5;
+    if (ca >= ab + bc) return (c + a) * 0.5;
+    const d3 e1 = b - a, e2 = c - a, n = cross(e1, e2);
+    const double n2 = norm2(n);
+    if (!(n2 > 0)) return (a + b) * 0.5;
+    return a + cross(e2 * norm2(e1) - e1 * norm2(e2), n) * (1.0 / (2.0 * n2));
+}
+
+bool d3_less(const d3& a, const d3& b)
+{
+    if (a.x != b.x) return a.x < b.x;
+    if (a.y != b.y) return a.y < b.y;
+    return a.z < b.z;
+}
+
+struct CellWork {
+    ClipCell cell;
+    std::vector<std::pair<double, int32_t>> knn;
+    std::vector<int32_t> tested;
+    std::vector<d3> corners, verified;
+    std::vector<int32_t> faces;
+    std::vector<Ball> balls;
+    std::vector<int32_t> list;
+    std::vector<uint32_t> stamp;
+    uint32_t gen = 0;
+};
+
+constexpr int kKnn = 24;
+// Float32 input positions break exact co-sphericity at the 1e-7 level; a
+// violation smaller than this is rounding noise of a degenerate corner.
+constexpr double kCornerSlack = 1e-6;
+
+// Voronoi cell of site s (index into P) clipped to the box [blo, bhi].
+void voronoi_cell(int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo, d3 bhi, CellWork& w)
+{
+    const d3 ps = P[s];
+    w.cell.init_box(blo - ps, bhi - ps);
+    kd.knn(ps, kKnn, s, w.knn);
+    w.tested.clear();
+    w.tested.push_back(s);
+    double r2max = w.cell.max_norm2();
+    bool final_by_radius = false;
+    for (const auto& e : w.knn) {
+        // A site at distance >= 2 * max corner radius cannot cut the cell.
+        if (e.first >= 4.0 * r2max) {
+            final_by_radius = true;
+            break;
+        }
+        const d3 n = P[e.second] - ps;
+        if (w.cell.clip(n, 0.5 * norm2(n), e.second)) r2max = w.cell.max_norm2();
+        w.tested.push_back(e.second);
+    }
+    std::sort(w.tested.begin(), w.tested.end());
+    if (!final_by_radius && (int)w.knn.size() == kKnn) {
+        // Sites beyond the kNN radius can only cut corners farther than half
+        // of it; check those corners exactly until none is violated.
+        const double dK2 = w.knn.back().first;
+        // Corners verified once stay valid: clipping only removes corners
+        // and adds new ones (bitwise copies survive), so only new corners
+        // need the exact check.
+        w.verified.clear();
+        for (size_t guard = 0; guard <= P.size(); ++guard) {
+            w.cell.corners(w.corners);
+            int32_t found = -1;
+            for (const d3& x : w.corners) {
+                const double r2 = norm2(x);
+                if (4.0 * r2 <= dK2) continue;
+                if (std::binary_search(w.verified.begin(), w.verified.end(), x, d3_less)) continue;
+                // A site closer than s by less than kCornerSlack (relative,
+                // in squared distance) is skipped: the cell then stays a
+                // superset of the exact one, and the walk's stop region and
+                // the lists are both built from this computed cell.
+                found = kd.nearest_below(ps + x, r2 * (1.0 - kCornerSlack), w.tested, nullptr, true);
+                if (found >= 0) break;
+                w.verified.insert(std::upper_bound(w.verified.begin(), w.verified.end(), x, d3_less), x);
+            }
+            if (found < 0) break;
+            const d3 n = P[found] - ps;
+            w.cell.clip(n, 0.5 * norm2(n), found);
+            w.tested.insert(std::upper_bound(w.tested.begin(), w.tested.end(), found), found);
+        }
+    }
+    w.cell.corners(w.corners);
+    w.cell.face_ids(w.faces);
+}
+
+void check_mesh(const p2m_mesh_desc& m)
+{
+    if (m.n_vertices < 0 || m.n_triangles < 0) throw Error(P2M_ERR_INVALID_ARG, "negative mesh size");
+    if (m.n_triangles == 0) throw Error(P2M_ERR_BAD_MESH, "mesh has no triangles");
+    if (!m.vertices || !m.triangles) throw Error(P2M_ERR_INVALID_ARG, "null mesh array");
+    if (m.n_vertices > std::numeric_limits<int32_t>::max() || m.n_triangles > (int64_t(1) << 29))
+        throw Error(P2M_ERR_OOM, "mesh too large for 32-bit indices");
+    for (int64_t i = 0; i < 3 * m.n_triangles; ++i) {
+        const int32_t v = m.triangles[i];
+        if (v < 0 || v >= m.n_vertices)
+            throw Error(P2M_ERR_BAD_MESH, "triangle " + std::to_string(i / 3) + " has vertex index " +
+                                              std::to_string(v) + " out of range");
+    }
+}
+
+}  // namespace
+
+void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructure& H)
+{
+    const auto t_start = clk::now();
+    check_mesh(mesh);
+    if (!(o.domain_scale >= 1.0f) || !(o.tau_scale > 0) || o.ring_sites < 0 ||
+        !(o.list_inflation_rel >= 0) || !(o.seed_cell_scale > 0) || o.seed_max_cells < 1)
+        throw Error(P2M_ERR_INVALID_ARG, "invalid build option");
+    const int nth = resolve_threads(o.n_threads);
+    const int64_t nV = mesh.n_vertices, nT = mesh.n_triangles;
+    H.n_vertices = nV;
+    H.n_triangles = nT;
+
+    // ---- sites: distinct positions of referenced vertices
+    std::vector<char> used(nV, 0);
+    for (int64_t i = 0; i < 3 * nT; ++i) used[mesh.triangles[i]] = 1;
+    std::vector<int32_t> ref;
+    for (int64_t v = 0; v < nV; ++v)
+        if (used[v]) {
+            const float* p = mesh.vertices + 3 * v;
+            if (!std::isfinite(p[0]) || !std::isfinite(p[1]) || !std::isfinite(p[2]))
+                throw Error(P2M_ERR_BAD_MESH, "vertex " + std::to_string(v) + " is not finite");
+            ref.push_back((int32_t)v);
+        }
+    std::sort(ref.begin(), ref.end(), [&](int32_t a, int32_t b) {
+        const float* p = mesh.vertices + 3 * (int64_t)a;
+        const float* q = mesh.vertices + 3 * (int64_t)b;
+        if (p[0] != q[0]) return p[0] < q[0];
+        if (p[1] != q[1]) return p[1] < q[1];
+        if (p[2] != q[2]) return p[2] < q[2];
+        return a < b;
+    });
+    std::vector<d3> P;
+    H.site_of_vertex.assign(nV, -1);
+    std::vector<int32_t> site_vertex;  // a representative vertex per vertex site
+    for (size_t i = 0; i < ref.size(); ++i) {
+        const float* p = mesh.vertices + 3 * (int64_t)ref[i];
+        if (i == 0 || std::memcmp(p, mesh.vertices + 3 * (int64_t)ref[i - 1], 12) != 0) {
+            P.push_back({p[0], p[1], p[2]});
+            site_vertex.push_back(ref[i]);
+        }
+        H.site_of_vertex[ref[i]] = (int32_t)P.size() - 1;
+    }
+    const int32_t nVS = (int32_t)P.size();
+
+    // ---- triangles (FP64 copies), boxes, edge length
+    std::vector<d3> T(3 * nT);
+    for (int64_t i = 0; i < 3 * nT; ++i) {
+        const float* p = mesh.vertices + 3 * (int64_t)mesh.triangles[i];
+        T[i] = {p[0], p[1], p[2]};
+    }
+    d3 mlo{INFINITY, INFINITY, INFINITY}, mhi{-INFINITY, -INFINITY, -INFINITY};
+    for (const d3& p : P) {
+        mlo = dmin3(mlo, p);
+        mhi = dmax3(mhi, p);
+    }
+    double diag = norm(mhi - mlo);
+    if (!(diag > 0)) diag = 1.0;
+    H.diag = diag;
+    double edge_sum = 0;
+    for (int64_t t = 0; t < nT; ++t)
+        edge_sum += norm(T[3 * t + 1] - T[3 * t]) + norm(T[3 * t + 2] - T[3 * t + 1]) + norm(T[3 * t] - T[3 * t + 2]);
+    double mean_edge = edge_sum / (3.0 * nT);
+    if (!(mean_edge > 0)) mean_edge = diag * 1e-3;
+    const d3 mc = (mlo + mhi) * 0.5;
+    auto padded_box = [&](double scale, d3& lo, d3& hi) {
+        d3 h = (mhi - mlo) * (0.5 * scale);
+        const double floor_h = 0.05 * diag * scale;
+        h = {std::max(h.x, floor_h), std::max(h.y, floor_h), std::max(h.z, floor_h)};
+        lo = mc - h;
+        hi = mc + h;
+    };
+    d3 blo, bhi;
+    padded_box(o.domain_scale, blo, bhi);
+    for (int k = 0; k < 3; ++k) {
+        H.dlo[k] = round_up(comp(blo, k));    // query box slightly inside the clip box
+        H.dhi[k] = round_down(comp(bhi, k));
+    }
+    const double delta = (double)o.list_inflation_rel * diag;
+
+    auto t0 = clk::now();
+    Bvh bvh;
+    bvh.build(T);
+    KdTree kd;
+    kd.build(P);
+    std::vector<CellWork> work(nth);
+    for (auto& w : work) w.stamp.assign(nT, 0);
+
+    // ---- pass 1 and ring-based augmentation (Sec. 3.2)
+    std::vector<char> is_aux(P.size(), 0);
+    // Cells (corners relative to the site, bounding-plane ids) of every site.
+    std::vector<std::vector<d3>> cell_corners(P.size());
+    std::vector<std::vector<int32_t>> cell_faces(P.size());
+    std::vector<char> cell_ok(P.size(), 0), cell_done(P.size(), 0);
+    int64_t n_dense = 0;
+    double t_vor1 = 0;
+    if (o.augment && nVS >= 5) {
+        const double tau = o.tau_scale * mean_edge;
+        struct Acc {
+            int64_t n = 0;       // distinct sites with a Voronoi vertex in this grid cell
+            int64_t nc = 0;      // Voronoi-vertex occurrences
+            d3 s{0, 0, 0};
+            double s2 = 0;
+        };
+        std::vector<std::unordered_map<uint64_t, Acc>> maps(nth);
+        const double tolb = 1e-9 * norm(bhi - blo);
+        const d3 glo = mlo - d3{tau, tau, tau};
+        auto key_of = [&](d3 u) {
+            const uint64_t ix = (uint64_t)((u.x - glo.x) / tau);
+            const uint64_t iy = (uint64_t)((u.y - glo.y) / tau);
+            const uint64_t iz = (uint64_t)((u.z - glo.z) / tau);
+            return ix | (iy << 21) | (iz << 42);
+        };
+        const double gmax = 2097150.0 * tau;
+        std::vector<std::vector<std::pair<uint64_t, d3>>> tmp(nth);
+        parallel_for(nVS, nth, [&](int64_t s, int tid) {
+            CellWork& w = work[tid];
+            voronoi_cell((int32_t)s, P, kd, blo, bhi, w);
+            cell_corners[s] = w.corners;
+            cell_faces[s] = w.faces;
+            cell_ok[s] = !w.cell.empty();
+            const d3 ps = P[s];
+            auto& kc = tmp[tid];
+            kc.clear();
+            for (const d3& x : w.corners) {
+                const d3 u = ps + x;
+                // finite Voronoi vertices only (not on the domain box)
+                if (u.x <= blo.x + tolb || u.y <= blo.y + tolb || u.z <= blo.z + tolb ||
+                    u.x >= bhi.x - tolb || u.y >= bhi.y - tolb || u.z >= bhi.z - tolb)
+                    continue;
+                // only clusters inside the mesh box can get auxiliary sites
+                if (u.x < mlo.x || u.y < mlo.y || u.z < mlo.z || u.x > mhi.x || u.y > mhi.y || u.z > mhi.z)
+                    continue;
+                if (u.x - glo.x > gmax || u.y - glo.y > gmax || u.z - glo.z > gmax) continue;
+                kc.push_back({key_of(u), u});
+            }
+            std::sort(kc.begin(), kc.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+            for (size_t i = 0; i < kc.size(); ++i) {
+                Acc& a = maps[tid][kc[i].first];
+                if (i == 0 || kc[i].first != kc[i - 1].first) a.n++;
+                a.nc++;
+                a.s = a.s + kc[i].second;
+                a.s2 += norm2(kc[i].second);
+            }
+        });
+        for (int t = 1; t < nth; ++t)
+            for (auto& kv : maps[t]) {
+                Acc& a = maps[0][kv.first];
+                a.n += kv.second.n;
+                a.nc += kv.second.nc;
+                a.s = a.s + kv.second.s;
+                a.s2 += kv.second.s2;
+            }
+        t_vor1 = secs_since(t0);
+        // Reference density: grid cells that hold mesh vertices (the
+        // sampling density near the surface the paper scales tau by).
+        std::unordered_map<uint64_t, char> site_cells;
+        for (int32_t s = 0; s < nVS; ++s) site_cells[key_of(P[s])] = 1;
+        std::vector<std::pair<uint64_t, Acc>> cells(maps[0].begin(), maps[0].end());
+        maps.clear();
+        std::sort(cells.begin(), cells.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        std::vector<int64_t> counts;
+        for (auto& c : cells)
+            if (site_cells.count(c.first)) counts.push_back(c.second.n);
+        int64_t median = 0;
+        if (!counts.empty()) {
+            std::nth_element(counts.begin(), counts.begin() + counts.size() / 2, counts.end());
+            median = counts[counts.size() / 2];
+        }
+        const double thr = std::max((double)o.dense_min_sites, (double)o.dense_rel * (double)median);
+        // icosahedron directions for the enclosing sphere
+        std::vector<d3> dirs;
+        {
+            const double g = (1.0 + std::sqrt(5.0)) / 2.0;
+            const double ico[12][3] = {{-1, g, 0}, {1, g, 0}, {-1, -g, 0}, {1, -g, 0}, {0, -1, g}, {0, 1, g},
+                                       {0, -1, -g}, {0, 1, -g}, {g, 0, -1}, {g, 0, 1}, {-g, 0, -1}, {-g, 0, 1}};
+            const int nr = std::min(o.ring_sites, 12);
+            for (int i = 0; i < nr; ++i) {
+                d3 d{ico[i][0], ico[i][1], ico[i][2]};
+                dirs.push_back(d * (1.0 / norm(d)));
+            }
+            // more than 12: golden-spiral directions
+            for (int i = 12; i < o.ring_sites; ++i) {
+                const double z = 1.0 - 2.0 * (i - 12 + 0.5) / (o.ring_sites - 12);
+                const double r = std::sqrt(std::max(0.0, 1.0 - z * z));
+                const double ph = i * 2.399963229728653;
+                dirs.push_back({r * std::cos(ph), r * std::sin(ph), z});
+            }
+        }
+        struct Cand {
+            d3 p;
+            double sep;
+        };
+        std::vector<Cand> centrals, rings;
+        for (auto& c : cells) {
+            if ((double)c.second.n < thr) continue;
+            ++n_dense;
+            const Acc& a = c.second;
+            const d3 pc = a.s * (1.0 / a.nc);
+            const double rms = std::sqrt(std::max(0.0, a.s2 / a.nc - norm2(pc)));
+            const double rho = std::min(std::max(3.0 * rms, tau), 3.0 * tau);
+            centrals.push_back({pc, 0.5 * tau});
+            for (const d3& d : dirs) rings.push_back({pc + d * rho, 0.5 * rho});
+        }
+        // accept centrals first, then ring sites; the overlap rule drops a
+        // candidate within its separation radius of an accepted one
+        std::vector<d3> acc;
+        const double cell_h = 0.25 * tau;
+        std::unordered_map<uint64_t, std::vector<int32_t>> grid;
+        auto gkey = [&](d3 p, int dx, int dy, int dz) {
+            const int64_t ix = (int64_t)std::floor((p.x - glo.x) / cell_h) + dx;
+            const int64_t iy = (int64_t)std::floor((p.y - glo.y) / cell_h) + dy;
+            const int64_t iz = (int64_t)std::floor((p.z - glo.z) / cell_h) + dz;
+            return (uint64_t)(ix & 0x1fffff) | ((uint64_t)(iy & 0x1fffff) << 21) | ((uint64_t)(iz & 0x1fffff) << 42);
+        };
+        const double min_site_sep = 1e-3 * mean_edge;
+        auto try_accept = [&](const Cand& c) {
+            if (c.p.x <= mlo.x || c.p.y <= mlo.y || c.p.z <= mlo.z || c.p.x >= mhi.x || c.p.y >= mhi.y || c.p.z >= mhi.z)
+                return;
+            const int reach = (int)std::ceil(c.sep / cell_h);
+            for (int dx = -reach; dx <= reach; ++dx)
+                for (int dy = -reach; dy <= reach; ++dy)
+                    for (int dz = -reach; dz <= reach; ++dz) {
+                        auto it = grid.find(gkey(c.p, dx, dy, dz));
+                        if (it == grid.end()) continue;
+                        for (int32_t j : it->second)
+                            if (norm2(acc[j] - c.p) < c.sep * c.sep) return;
+                    }
+            double d2;
+            kd.nearest(c.p, &d2);
+            if (d2 < min_site_sep * min_site_sep) return;
+            // round to float32 now: sites are stored and compared in float32 positions
+            const d3 pf{(float)c.p.x, (float)c.p.y, (float)c.p.z};
+            grid[gkey(pf, 0, 0, 0)].push_back((int32_t)acc.size());
+            acc.push_back(pf);
+        };
+        for (const Cand& c : centrals) try_accept(c);
+        for (const Cand& c : rings) try_accept(c);
+        if (!acc.empty()) {
+            // drop auxiliary sites whose cells reach the domain box (an
+            // unbounded cell would get a list of the whole mesh)
+            std::vector<d3> aux = acc;
+            for (int iter = 0; iter < 6 && !aux.empty(); ++iter) {
+                std::vector<d3> PP = P;
+                PP.insert(PP.end(), aux.begin(), aux.end());
+                KdTree kd2;
+                kd2.build(PP);
+                std::vector<char> drop(aux.size(), 0);
+                parallel_for((int64_t)aux.size(), nth, [&](int64_t i, int tid) {
+                    CellWork& w = work[tid];
+                    voronoi_cell((int32_t)(nVS + i), PP, kd2, blo, bhi, w);
+                    if (w.faces.empty() || w.faces.front() < 0 || w.cell.empty()) drop[i] = 1;
+                }, 8);
+                std::vector<d3> keep;
+                for (size_t i = 0; i < aux.size(); ++i)
+                    if (!drop[i]) keep.push_back(aux[i]);
+                const bool stable = keep.size() == aux.size();
+                aux.swap(keep);
+                if (stable) break;
+            }
+            // Vertex cells reused from pass 1 unless an auxiliary site is
+            // closer than the site to one of their corners.
+            KdTree kda;
+            kda.build(aux);
+            static const std::vector<int32_t> none;
+            parallel_for(nVS, nth, [&](int64_t s, int) {
+                bool hit = false;
+                for (const d3& x : cell_corners[s])
+                    if (!aux.empty() && kda.nearest_below(P[s] + x, norm2(x), none) >= 0) { hit = true; break; }
+                cell_done[s] = !hit;
+            }, 256);
+            P.insert(P.end(), aux.begin(), aux.end());
+            is_aux.assign(P.size(), 0);
+            for (size_t i = nVS; i < P.size(); ++i) is_aux[i] = 1;
+            kd.build(P);
+        } else {
+            std::fill(cell_done.begin(), cell_done.end(), 1);
+        }
+    }
+    H.stats.t_optimize_s = secs_since(t0) - t_vor1;
+    if (!o.augment || nVS < 5) std::fill(cell_done.begin(), cell_done.end(), 0);
+    const int32_t nS = (int32_t)P.size();
+    if ((int64_t)nS > std::numeric_limits<int32_t>::max() / 2) throw Error(P2M_ERR_OOM, "too many sites");
+
+    // ---- pass 2: remaining cells, then neighbours and interception lists
+    t0 = clk::now();
+    cell_corners.resize(nS);
+    cell_faces.resize(nS);
+    cell_ok.resize(nS, 0);
+    cell_done.resize(nS, 0);
+    parallel_for(nS, nth, [&](int64_t s, int tid) {
+        if (cell_done[s]) return;
+        CellWork& w = work[tid];
+        voronoi_cell((int32_t)s, P, kd, blo, bhi, w);
+        cell_corners[s] = w.corners;
+        cell_faces[s] = w.faces;
+        cell_ok[s] = !w.cell.empty();
+    }, 16);
+    H.stats.t_voronoi_s = t_vor1 + secs_since(t0);
+    t0 = clk::now();
+    std::vector<std::vector<int32_t>> nbr(nS), lists(nS);
+    std::vector<char> bad(nS, 0);
+    parallel_for(nS, nth, [&](int64_t s, int tid) {
+        CellWork& w = work[tid];
+        if (!cell_ok[s]) { bad[s] = 1; return; }
+        w.corners.swap(cell_corners[s]);
+        std::vector<d3>().swap(cell_corners[s]);
+        auto& nb = nbr[s];
+        for (int32_t f : cell_faces[s])
+            if (f >= 0) nb.push_back(f);
+        std::vector<int32_t>().swap(cell_faces[s]);
+        const d3 ps = P[s];
+        d3 v = ps;  // reference point on the mesh
+        if (is_aux[s]) bvh.closest(ps, nullptr, &v);
+        w.balls.clear();
+        if (is_aux[s] && o.aux_list_mode == 0) {
+            // Eq. (8): one sphere about s containing every corner ball
+            double r = 0;
+            for (const d3& x : w.corners) r = std::max(r, norm(x) + norm(ps + x - v));
+            w.balls.push_back({ps, r + delta});
+        } else {
+            for (const d3& x : w.corners) {
+                const d3 u = ps + x;
+                w.balls.push_back({u, norm(u - v) + delta});
+            }
+            // drop balls contained in another ball
+            std::sort(w.balls.begin(), w.balls.end(), [](const Ball& a, const Ball& b) { return a.r > b.r; });
+            size_t k = 0;
+            for (size_t i = 0; i < w.balls.size(); ++i) {
+                bool inside = false;
+                for (size_t j = 0; j < k && !inside; ++j)
+                    inside = norm(w.balls[i].c - w.balls[j].c) + w.balls[i].r <= w.balls[j].r;
+                if (!inside) w.balls[k++] = w.balls[i];
+            }
+            w.balls.resize(k);
+        }
+        w.list.clear();
+        if (++w.gen == 0) {
+            std::fill(w.stamp.begin(), w.stamp.end(), 0);
+            w.gen = 1;
+        }
+        bvh.query_union(w.balls, w.list, w.stamp, w.gen);
+        lists[s] = w.list;
+        if (w.list.empty()) bad[s] = 2;
+    }, 16);
+    for (int32_t s = 0; s < nS; ++s)
+        if (bad[s]) throw Error(P2M_ERR_INTERNAL, std::string(bad[s] == 1 ? "empty Voronoi cell" : "empty interception list") +
+                                                      " at site " + std::to_string(s));
+    H.stats.t_lists_s = secs_since(t0);
+
+    // ---- layout
+    t0 = clk::now();
+    // triangle slots: BVH leaf order
+    const std::vector<int32_t>& torder = bvh.order();
+    std::vector<int32_t> slot_of(nT);
+    for (int64_t i = 0; i < nT; ++i) slot_of[torder[i]] = (int32_t)i;
+    // bounding spheres (user order)
+    std::vector<float> sph(4 * nT);
+    for (int64_t t = 0; t < nT; ++t) {
+        const d3 a = T[3 * t], b = T[3 * t + 1], c = T[3 * t + 2];
+        const d3 cc = min_sphere_center(a, b, c);
+        const float cx = (float)cc.x, cy = (float)cc.y, cz = (float)cc.z;
+        const d3 cf{cx, cy, cz};
+        const double r = std::max({norm(a - cf), norm(b - cf), norm(c - cf)});
+        sph[4 * t] = cx;
+        sph[4 * t + 1] = cy;
+        sph[4 * t + 2] = cz;
+        sph[4 * t + 3] = round_up(r * (1.0 + 1e-6));
+    }
+    // site order: Morton code of position
+    std::vector<int32_t> sorder(nS);
+    std::iota(sorder.begin(), sorder.end(), 0);
+    {
+        const double ext = std::max({mhi.x - mlo.x, mhi.y - mlo.y, mhi.z - mlo.z, 1e-30});
+        const double inv = 2097151.0 / ext;
+        std::vector<uint64_t> key(nS);
+        for (int32_t s = 0; s < nS; ++s) key[s] = morton_of(P[s], mlo, inv);
+        std::stable_sort(sorder.begin(), sorder.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    }
+    std::vector<int32_t> new_id(nS);
+    for (int32_t i = 0; i < nS; ++i) new_id[sorder[i]] = i;
+
+    H.n_sites = nS;
+    H.n_aux = nS - nVS;
+    H.site_xyz.assign(4 * (size_t)nS, 0.f);
+    H.site_rng.assign(4 * (size_t)nS, 0);
+    H.site_is_aux.assign(nS, 0);
+    int64_t adj_nnz = 0, list_nnz = 0, adj_max = 0, list_max = 0;
+    for (int32_t s = 0; s < nS; ++s) {
+        adj_nnz += (int64_t)nbr[s].size();
+        list_nnz += (int64_t)lists[s].size();
+        adj_max = std::max<int64_t>(adj_max, nbr[s].size());
+        list_max = std::max<int64_t>(list_max, lists[s].size());
+    }
+    if (adj_nnz > std::numeric_limits<int32_t>::max() || list_nnz > std::numeric_limits<int32_t>::max())
+        throw Error(P2M_ERR_OOM, "interception lists exceed 2^31 entries");
+    H.adj.resize(4 * (size_t)adj_nnz);
+    H.list_sph.resize(4 * (size_t)list_nnz);
+    H.list_aux.resize(2 * (size_t)list_nnz);
+    std::vector<int64_t> adj_off(nS + 1, 0), list_off(nS + 1, 0);
+    for (int32_t i = 0; i < nS; ++i) {
+        const int32_t s = sorder[i];
+        adj_off[i + 1] = adj_off[i] + (int64_t)nbr[s].size();
+        list_off[i + 1] = list_off[i] + (int64_t)lists[s].size();
+    }
+    parallel_for(nS, nth, [&](int64_t i, int) {
+        const int32_t s = sorder[i];
+        const float sx = (float)P[s].x, sy = (float)P[s].y, sz = (float)P[s].z;
+        H.site_xyz[4 * i] = sx;
+        H.site_xyz[4 * i + 1] = sy;
+        H.site_xyz[4 * i + 2] = sz;
+        H.site_is_aux[i] = is_aux[s];
+        H.site_rng[4 * i] = (int32_t)adj_off[i];
+        H.site_rng[4 * i + 1] = (int32_t)adj_off[i + 1];
+        H.site_rng[4 * i + 2] = (int32_t)list_off[i];
+        H.site_rng[4 * i + 3] = (int32_t)list_off[i + 1];
+        std::vector<int32_t> nb(nbr[s].size());
+        for (size_t k = 0; k < nb.size(); ++k) nb[k] = new_id[nbr[s][k]];
+        std::sort(nb.begin(), nb.end());
+        for (size_t k = 0; k < nb.size(); ++k) {
+            const int64_t e = adj_off[i] + (int64_t)k;
+            const int32_t t = sorder[nb[k]];
+            H.adj[4 * e] = (float)P[t].x;
+            H.adj[4 * e + 1] = (float)P[t].y;
+            H.adj[4 * e + 2] = (float)P[t].z;
+            H.adj[4 * e + 3] = ibits(nb[k]);
+        }
+        // list entries sorted by ell = |s - c| - r (rounded down)
+        const d3 sf{sx, sy, sz};
+        std::vector<std::pair<float, int32_t>> ent(lists[s].size());
+        for (size_t k = 0; k < ent.size(); ++k) {
+            const int32_t t = lists[s][k];
+            const d3 c{sph[4 * t], sph[4 * t + 1], sph[4 * t + 2]};
+            ent[k] = {round_down(norm(sf - c) - (double)sph[4 * t + 3]), slot_of[t]};
+        }
+        std::sort(ent.begin(), ent.end());
+        for (size_t k = 0; k < ent.size(); ++k) {
+            const int64_t e = list_off[i] + (int64_t)k;
+            const int32_t t = torder[ent[k].second];
+            std::memcpy(&H.list_sph[4 * e], &sph[4 * t], 16);
+            H.list_aux[2 * e] = ent[k].second;
+            H.list_aux[2 * e + 1] = fbits(ent[k].first);
+        }
+    }, 256);
+    for (int64_t v = 0; v < nV; ++v)
+        if (H.site_of_vertex[v] >= 0) H.site_of_vertex[v] = new_id[H.site_of_vertex[v]];
+
+    // triangle records in slot order
+    H.tri_rec.resize(12 * (size_t)nT);
+    H.tri_user.resize(nT);
+    H.tri_vid.resize(4 * (size_t)nT);
+    for (int64_t i = 0; i < nT; ++i) {
+        const int32_t t = torder[i];
+        const d3 a = T[3 * t], b = T[3 * t + 1], c = T[3 * t + 2];
+        const float e1x = (float)(b.x - a.x), e1y = (float)(b.y - a.y), e1z = (float)(b.z - a.z);
+        const float e2x = (float)(c.x - a.x), e2y = (float)(c.y - a.y), e2z = (float)(c.z - a.z);
+        const double g11 = (double)e1x * e1x + (double)e1y * e1y + (double)e1z * e1z;
+        const double g12 = (double)e1x * e2x + (double)e1y * e2y + (double)e1z * e2z;
+        const double g22 = (double)e2x * e2x + (double)e2y * e2y + (double)e2z * e2z;
+        float* r = &H.tri_rec[12 * i];
+        r[0] = (float)a.x; r[1] = (float)a.y; r[2] = (float)a.z; r[3] = (float)g11;
+        r[4] = e1x; r[5] = e1y; r[6] = e1z; r[7] = (float)g12;
+        r[8] = e2x; r[9] = e2y; r[10] = e2z; r[11] = (float)g22;
+        H.tri_user[i] = t;
+        H.tri_vid[4 * i] = mesh.triangles[3 * t];
+        H.tri_vid[4 * i + 1] = mesh.triangles[3 * t + 1];
+        H.tri_vid[4 * i + 2] = mesh.triangles[3 * t + 2];
+        H.tri_vid[4 * i + 3] = 0;
+    }
+    // fallback BVH nodes
+    const auto& nodes = bvh.nodes();
+    H.bvh.resize(8 * nodes.size());
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const auto& n = nodes[i];
+        float* r = &H.bvh[8 * i];
+        r[0] = round_down(n.lo.x); r[1] = round_down(n.lo.y); r[2] = round_down(n.lo.z);
+        r[3] = ibits(n.left_or_begin);
+        r[4] = round_up(n.hi.x); r[5] = round_up(n.hi.y); r[6] = round_up(n.hi.z);
+        r[7] = ibits(n.right_or_count);
+    }
+    // seed grid over the mesh box x1.25: exact nearest site of each cell centre
+    {
+        d3 glo, ghi;
+        padded_box(1.25, glo, ghi);
+        double cell = o.seed_cell_scale * mean_edge;
+        const d3 ext = ghi - glo;
+        auto dims = [&](double c, int64_t* g) {
+            g[0] = std::max<int64_t>(1, (int64_t)std::ceil(ext.x / c));
+            g[1] = std::max<int64_t>(1, (int64_t)std::ceil(ext.y / c));
+            g[2] = std::max<int64_t>(1, (int64_t)std::ceil(ext.z / c));
+            return g[0] * g[1] * g[2];
+        };
+        int64_t g[3];
+        int64_t ncell = dims(cell, g);
+        while (ncell > o.seed_max_cells || g[0] > 2048 || g[1] > 2048 || g[2] > 2048) {
+            cell *= std::max(1.01, std::cbrt((double)ncell / (double)o.seed_max_cells));
+            ncell = dims(cell, g);
+        }
+        H.gcell = (float)cell;
+        for (int k = 0; k < 3; ++k) {
+            H.gdim[k] = (int32_t)g[k];
+            H.gorg[k] = (float)comp(glo, k);
+        }
+        H.seed.resize(ncell);
+        const double gc = (double)H.gcell;
+        parallel_for(ncell, nth, [&](int64_t idx, int) {
+            const int64_t ix = idx % g[0], iy = (idx / g[0]) % g[1], iz = idx / (g[0] * g[1]);
+            const d3 c{H.gorg[0] + (ix + 0.5) * gc, H.gorg[1] + (iy + 0.5) * gc, H.gorg[2] + (iz + 0.5) * gc};
+            H.seed[idx] = new_id[kd.nearest(c)];
+        }, 1024);
+    }
+    H.stats.t_layout_s = secs_since(t0);
+
+    H.stats.n_vertices = nV;
+    H.stats.n_triangles = nT;
+    H.stats.n_sites = nS;
+    H.stats.n_vertex_sites = nVS;
+    H.stats.n_aux_sites = nS - nVS;
+    H.stats.n_dense_cells = n_dense;
+    H.stats.adj_nnz = adj_nnz;
+    H.stats.adj_max = adj_max;
+    H.stats.adj_avg = (double)adj_nnz / nS;
+    H.stats.list_nnz = list_nnz;
+    H.stats.list_max = list_max;
+    H.stats.list_avg = (double)list_nnz / nS;
+    for (int k = 0; k < 3; ++k) H.stats.seed_dims[k] = H.gdim[k];
+    H.stats.diag = diag;
+    H.stats.t_total_s = secs_since(t_start);
+}
+
+}  // namespace p2m

@@ -1,0 +1,146 @@
+#include "cell.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace p2m {
+
+void ClipCell::init_box(d3 lo, d3 hi)
+{
+    faces_.clear();
+    v_.clear();
+    auto add = [&](int32_t id, std::initializer_list<d3> pts) {
+        faces_.push_back({id, (int32_t)v_.size(), (int32_t)pts.size()});
+        for (const d3& p : pts) v_.push_back(p);
+    };
+    add(-1, {{lo.x, lo.y, lo.z}, {lo.x, lo.y, hi.z}, {lo.x, hi.y, hi.z}, {lo.x, hi.y, lo.z}});
+    add(-2, {{hi.x, lo.y, lo.z}, {hi.x, hi.y, lo.z}, {hi.x, hi.y, hi.z}, {hi.x, lo.y, hi.z}});
+    add(-3, {{lo.x, lo.y, lo.z}, {hi.x, lo.y, lo.z}, {hi.x, lo.y, hi.z}, {lo.x, lo.y, hi.z}});
+    add(-4, {{lo.x, hi.y, lo.z}, {lo.x, hi.y, hi.z}, {hi.x, hi.y, hi.z}, {hi.x, hi.y, lo.z}});
+    add(-5, {{lo.x, lo.y, lo.z}, {lo.x, hi.y, lo.z}, {hi.x, hi.y, lo.z}, {hi.x, lo.y, lo.z}});
+    add(-6, {{lo.x, lo.y, hi.z}, {hi.x, lo.y, hi.z}, {hi.x, hi.y, hi.z}, {lo.x, hi.y, hi.z}});
+    scale_ = std::sqrt(max_norm2());
+}
+
+double ClipCell::max_norm2() const
+{
+    double m = 0;
+    for (const d3& p : v_) m = std::max(m, norm2(p));
+    return m;
+}
+
+bool ClipCell::clip(d3 n, double h, int32_t id)
+{
+    const double nn = norm(n);
+    if (!(nn > 0)) return false;
+    const double eps = 1e-12 * nn * scale_;
+    sd_.resize(v_.size());
+    bool any_out = false;
+    for (size_t i = 0; i < v_.size(); ++i) {
+        sd_[i] = dot(n, v_[i]) - h;
+        any_out |= sd_[i] > eps;
+    }
+    if (!any_out) return false;
+
+    nfaces_.clear();
+    nv_.clear();
+    cut_.clear();
+    for (const Face& f : faces_) {
+        const int32_t nb = (int32_t)nv_.size();
+        for (int32_t i = 0; i < f.count; ++i) {
+            const int32_t a = f.begin + i;
+            const int32_t b = f.begin + (i + 1) % f.count;
+            const double sa = sd_[a], sb = sd_[b];
+            if (sa <= eps) {
+                nv_.push_back(v_[a]);
+                if (sa >= -eps) cut_.push_back(v_[a]);
+            }
+            if ((sa < -eps && sb > eps) || (sa > eps && sb < -eps)) {
+                // Interpolate from the inside end to the outside end so that
+                // both faces sharing this edge produce the same point.
+                const bool a_in = sa < 0;
+                const d3 pin = a_in ? v_[a] : v_[b];
+                const d3 pout = a_in ? v_[b] : v_[a];
+                const double sin_ = a_in ? sa : sb, sout = a_in ? sb : sa;
+                const double t = sin_ / (sin_ - sout);
+                const d3 x = pin + (pout - pin) * t;
+                nv_.push_back(x);
+                cut_.push_back(x);
+            }
+        }
+        const int32_t cnt = (int32_t)nv_.size() - nb;
+        if (cnt >= 3) nfaces_.push_back({f.id, nb, cnt});
+        else nv_.resize(nb);
+    }
+
+    // The new face: the cut points ordered by angle around their centroid.
+    if (cut_.size() >= 3) {
+        d3 c{0, 0, 0};
+        for (const d3& p : cut_) c = c + p;
+        c = c * (1.0 / cut_.size());
+        const d3 nh = n * (1.0 / nn);
+        d3 ax = std::fabs(nh.x) < 0.57 ? d3{1, 0, 0} : (std::fabs(nh.y) < 0.57 ? d3{0, 1, 0} : d3{0, 0, 1});
+        d3 u = cross(nh, ax);
+        u = u * (1.0 / norm(u));
+        const d3 w = cross(nh, u);
+        std::vector<std::pair<double, int32_t>> ang(cut_.size());
+        for (size_t i = 0; i < cut_.size(); ++i) {
+            const d3 r = cut_[i] - c;
+            ang[i] = {std::atan2(dot(r, w), dot(r, u)), (int32_t)i};
+        }
+        std::sort(ang.begin(), ang.end());
+        const double tol2 = (1e-11 * scale_) * (1e-11 * scale_);
+        const int32_t nb = (int32_t)nv_.size();
+        for (const auto& e : ang) {
+            const d3& p = cut_[e.second];
+            if ((int32_t)nv_.size() > nb && norm2(p - nv_.back()) <= tol2) continue;
+            nv_.push_back(p);
+        }
+        while ((int32_t)nv_.size() - nb > 1 && norm2(nv_.back() - nv_[nb]) <= tol2) nv_.pop_back();
+        const int32_t cnt = (int32_t)nv_.size() - nb;
+        if (cnt >= 3) nfaces_.push_back({id, nb, cnt});
+        else nv_.resize(nb);
+    }
+    faces_.swap(nfaces_);
+    v_.swap(nv_);
+    return true;
+}
+
+void ClipCell::corners(std::vector<d3>& out) const
+{
+    out.assign(v_.begin(), v_.end());
+    std::sort(out.begin(), out.end(), [](const d3& a, const d3& b) {
+        if (a.x != b.x) return a.x < b.x;
+        if (a.y != b.y) return a.y < b.y;
+        return a.z < b.z;
+    });
+    const double tol = 1e-11 * scale_;
+    const double tol2 = tol * tol;
+    std::vector<char> dup(out.size(), 0);
+    for (size_t i = 0; i < out.size(); ++i) {
+        if (dup[i]) continue;
+        for (size_t j = i + 1; j < out.size() && out[j].x - out[i].x <= tol; ++j)
+            if (!dup[j] && norm2(out[j] - out[i]) <= tol2) dup[j] = 1;
+    }
+    size_t k = 0;
+    for (size_t i = 0; i < out.size(); ++i)
+        if (!dup[i]) out[k++] = out[i];
+    out.resize(k);
+}
+
+void ClipCell::face_ids(std::vector<int32_t>& out) const
+{
+    out.clear();
+    const double min_area = (1e-12 * scale_) * (1e-12 * scale_);
+    for (const Face& f : faces_) {
+        d3 a{0, 0, 0};
+        const d3& p0 = v_[f.begin];
+        for (int32_t i = 1; i + 1 < f.count; ++i)
+            a = a + cross(v_[f.begin + i] - p0, v_[f.begin + i + 1] - p0);
+        if (0.5 * norm(a) > min_area) out.push_back(f.id);
+    }
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+}
+
+}  // namespace p2m

@@ -1,0 +1,170 @@
+#include "kdtree.h"
+
+#include <algorithm>
+#include <limits>
+#include <queue>
+
+namespace p2m {
+
+namespace {
+constexpr int kLeaf = 8;
+}
+
+void KdTree::build(const std::vector<d3>& pts)
+{
+    pts_ = pts;
+    idx_.resize(pts.size());
+    for (size_t i = 0; i < pts.size(); ++i) idx_[i] = (int32_t)i;
+    nodes_.clear();
+    nodes_.reserve(2 * pts.size() / kLeaf + 2);
+    if (!pts.empty()) build_rec(0, (int32_t)pts.size());
+}
+
+int32_t KdTree::build_rec(int32_t b, int32_t e)
+{
+    Node n;
+    n.lo = {INFINITY, INFINITY, INFINITY};
+    n.hi = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t i = b; i < e; ++i) {
+        n.lo = dmin3(n.lo, pts_[idx_[i]]);
+        n.hi = dmax3(n.hi, pts_[idx_[i]]);
+    }
+    n.begin = b;
+    n.end = e;
+    n.left = n.right = -1;
+    int32_t id = (int32_t)nodes_.size();
+    nodes_.push_back(n);
+    if (e - b <= kLeaf) return id;
+    d3 ext = n.hi - n.lo;
+    int axis = (ext.x >= ext.y && ext.x >= ext.z) ? 0 : (ext.y >= ext.z ? 1 : 2);
+    int32_t m = b + (e - b) / 2;
+    std::nth_element(idx_.begin() + b, idx_.begin() + m, idx_.begin() + e,
+                     [&](int32_t i, int32_t j) { return comp(pts_[i], axis) < comp(pts_[j], axis); });
+    int32_t l = build_rec(b, m);
+    int32_t r = build_rec(m, e);
+    nodes_[id].left = l;
+    nodes_[id].right = r;
+    return id;
+}
+
+double KdTree::box_d2(const Node& n, d3 q)
+{
+    double dx = std::max({n.lo.x - q.x, 0.0, q.x - n.hi.x});
+    double dy = std::max({n.lo.y - q.y, 0.0, q.y - n.hi.y});
+    double dz = std::max({n.lo.z - q.z, 0.0, q.z - n.hi.z});
+    return dx * dx + dy * dy + dz * dz;
+}
+
+void KdTree::knn(d3 q, int k, int32_t skip, std::vector<std::pair<double, int32_t>>& out) const
+{
+    out.clear();
+    if (nodes_.empty() || k <= 0) return;
+    // max-heap of the current best k
+    std::priority_queue<std::pair<double, int32_t>> best;
+    struct Item { double d2; int32_t node; };
+    std::vector<Item> stack;
+    stack.push_back({box_d2(nodes_[0], q), 0});
+    while (!stack.empty()) {
+        Item it = stack.back();
+        stack.pop_back();
+        if ((int)best.size() == k && it.d2 >= best.top().first) continue;
+        const Node& n = nodes_[it.node];
+        if (n.left < 0) {
+            for (int32_t i = n.begin; i < n.end; ++i) {
+                int32_t p = idx_[i];
+                if (p == skip) continue;
+                double d2 = norm2(pts_[p] - q);
+                if ((int)best.size() < k) best.push({d2, p});
+                else if (d2 < best.top().first || (d2 == best.top().first && p < best.top().second)) {
+                    best.pop();
+                    best.push({d2, p});
+                }
+            }
+            continue;
+        }
+        double dl = box_d2(nodes_[n.left], q), dr = box_d2(nodes_[n.right], q);
+        if (dl <= dr) {
+            stack.push_back({dr, n.right});
+            stack.push_back({dl, n.left});
+        } else {
+            stack.push_back({dl, n.left});
+            stack.push_back({dr, n.right});
+        }
+    }
+    out.resize(best.size());
+    for (size_t i = out.size(); i-- > 0;) {
+        out[i] = best.top();
+        best.pop();
+    }
+}
+
+int32_t KdTree::nearest_below(d3 q, double limit2, const std::vector<int32_t>& excluded,
+                              double* d2_out, bool first) const
+{
+    if (nodes_.empty()) return -1;
+    double best = limit2;
+    int32_t bi = -1;
+    struct Item { double d2; int32_t node; };
+    std::vector<Item> stack;
+    stack.reserve(64);
+    stack.push_back({box_d2(nodes_[0], q), 0});
+    while (!stack.empty()) {
+        Item it = stack.back();
+        stack.pop_back();
+        if (it.d2 >= best) continue;
+        const Node& n = nodes_[it.node];
+        if (n.left < 0) {
+            for (int32_t i = n.begin; i < n.end; ++i) {
+                int32_t p = idx_[i];
+                double d2 = norm2(pts_[p] - q);
+                if (d2 < best || (d2 == best && bi >= 0 && p < bi)) {
+                    if (std::binary_search(excluded.begin(), excluded.end(), p)) continue;
+                    best = d2;
+                    bi = p;
+                    if (first) {
+                        if (d2_out) *d2_out = best;
+                        return bi;
+                    }
+                }
+            }
+            continue;
+        }
+        double dl = box_d2(nodes_[n.left], q), dr = box_d2(nodes_[n.right], q);
+        if (dl <= dr) {
+            stack.push_back({dr, n.right});
+            stack.push_back({dl, n.left});
+        } else {
+            stack.push_back({dl, n.left});
+            stack.push_back({dr, n.right});
+        }
+    }
+    if (d2_out) *d2_out = best;
+    return bi;
+}
+
+int32_t KdTree::nearest(d3 q, double* d2_out) const
+{
+    static const std::vector<int32_t> none;
+    return nearest_below(q, std::numeric_limits<double>::infinity(), none, d2_out);
+}
+
+void KdTree::radius(d3 q, double r2, std::vector<int32_t>& out) const
+{
+    if (nodes_.empty()) return;
+    std::vector<int32_t> stack{0};
+    while (!stack.empty()) {
+        int32_t ni = stack.back();
+        stack.pop_back();
+        const Node& n = nodes_[ni];
+        if (box_d2(n, q) > r2) continue;
+        if (n.left < 0) {
+            for (int32_t i = n.begin; i < n.end; ++i)
+                if (norm2(pts_[idx_[i]] - q) <= r2) out.push_back(idx_[i]);
+            continue;
+        }
+        stack.push_back(n.left);
+        stack.push_back(n.right);
+    }
+}
+
+}  // namespace p2m
