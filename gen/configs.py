@@ -47,9 +47,9 @@ def config_c0(n_queries=10_000):
     return dict(name="C0 uv-sphere 32x16", V=V, F=F, Q=Q, D=_diag(V))
 
 
-def config_c1(n_uniform=1_000_000, n_near=1_000_000):
+def config_c1(n_uniform=1_000_000, n_near=1_000_000, n_seg=512, n_ring=128):
     rng = np.random.default_rng(SEED_BASE + 1)
-    V, F = M.cylinder_cone(512, 128)
+    V, F = M.cylinder_cone(n_seg, n_ring)
     Q = _mixed_queries(rng, V, F, n_uniform, n_near, 0.01)
     return dict(name="C1 cylinder+cone 512x128", V=V, F=F, Q=Q, D=_diag(V))
 

@@ -348,10 +348,21 @@ int32_t p2m_batch_bind(p2m_batch b, const float* d_points, float* d_out_dist, in
         (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
-    e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = b->enqueue(st);
-    e = hipStreamEndCapture(st, &b->graph);
+    // Record into a private stream (the caller's may be the null stream,
+    // which cannot be captured); the graph is launched on the caller's stream.
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    hipError_t le = b->enqueue(cap);
+    e = hipStreamEndCapture(cap, &b->graph);
+    (void)hipStreamDestroy(cap);
     if (le != hipSuccess) return hip_fail(le, "captured launch");
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);

@@ -1,0 +1,107 @@
+"""Batched multi-mesh queries: one persistent, graph-captured launch must give
+exactly the per-mesh plain-launch results (the per-point code is shared)."""
+import os
+
+import numpy as np
+import pytest
+
+import gen
+
+from gpu_util import check_forward, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_00429_amd as p2m
+    return p2m
+
+
+@pytest.fixture(scope="module")
+def c4_small(dev):
+    """The C4 recipe with the first 10 meshes, triangle counts capped at 8,000
+    and 5% of the points (host preprocessing of the full set takes minutes)."""
+    plan = [(k, min(t, 8000), q) for k, t, q in gen.c4_plan()[:10]]
+    cfg = gen.config_c4(plan, query_scale=0.05)
+    meshes = [dev.Mesh(c["V"], c["F"]) for c in cfg]
+    return cfg, meshes
+
+
+def concat_points(cfg):
+    Q = np.concatenate([c["Q"] for c in cfg], 0)
+    off = np.concatenate([[0], np.cumsum([len(c["Q"]) for c in cfg])])
+    return Q, off
+
+
+def test_batched_forward_equals_plain(dev, c4_small, tmp_path):
+    cfg, meshes = c4_small
+    Q, off = concat_points(cfg)
+    n = len(Q)
+    q = torch.from_numpy(Q).cuda()
+    dist = torch.empty(n, device="cuda")
+    tri = torch.empty(n, dtype=torch.int32, device="cuda")
+    cl = torch.empty((n, 3), device="cuda")
+    cache = str(tmp_path / "tune.txt")
+    b = dev.Batch(meshes, [len(c["Q"]) for c in cfg], autotune=True, cache_path=cache)
+    b.bind(q, dist, tri, cl)
+    ref = []
+    for i, m in enumerate(meshes):
+        ref.append(dev.query(m, q[off[i]:off[i + 1]].contiguous()))
+    for rep in range(3):
+        dist.fill_(-1.0)
+        tri.fill_(-7)
+        b.launch()
+        torch.cuda.synchronize()
+        # eager work between graph replays
+        _ = (q * 2).sum().item()
+        for i in range(len(meshes)):
+            s = slice(off[i], off[i + 1])
+            assert torch.equal(dist[s], ref[i][0]), (rep, i)
+            assert torch.equal(tri[s], ref[i][1]), (rep, i)
+            assert torch.equal(cl[s], ref[i][2]), (rep, i)
+    # a second batch over the same sizes takes the cached configuration
+    cfg1 = b.config()
+    b2 = dev.Batch(meshes, [len(c["Q"]) for c in cfg], autotune=True, cache_path=cache)
+    b2.bind(q, dist, tri, cl)
+    assert b2.config() == cfg1
+    assert os.path.exists(cache)
+    # and both match the oracle on a sample
+    for i in (0, len(meshes) - 1):
+        s = slice(off[i], off[i + 1])
+        idx = np.arange(off[i], min(off[i + 1], off[i] + 1500))
+        check_forward(cfg[i]["V"], cfg[i]["F"], Q[idx], to_np(dist)[idx], to_np(tri)[idx], to_np(cl)[idx],
+                      cfg[i]["D"], label=cfg[i]["name"])
+
+
+def test_batched_fused_equals_plain(dev, c4_small):
+    cfg, meshes = c4_small
+    Q, off = concat_points(cfg)
+    n = len(Q)
+    rng = np.random.default_rng(31)
+    q = torch.from_numpy(Q).cuda()
+    g = torch.from_numpy(rng.normal(size=n).astype(np.float32)).cuda()
+    dist = torch.empty(n, device="cuda")
+    tri = torch.empty(n, dtype=torch.int32, device="cuda")
+    cl = torch.empty((n, 3), device="cuda")
+    gq = torch.empty((n, 3), device="cuda")
+    gvs = [torch.zeros((len(m.V), 3), device="cuda") for m in meshes]
+    b = dev.Batch(meshes, [len(c["Q"]) for c in cfg], autotune=False)
+    b.bind(q, dist, tri, cl, grad_dist=g, grad_points=gq, grad_vertices=gvs)
+    for rep in range(2):
+        for t in gvs:
+            t.zero_()
+        b.launch()
+        torch.cuda.synchronize()
+        for i, m in enumerate(meshes):
+            s = slice(off[i], off[i + 1])
+            gv_ref = torch.zeros_like(gvs[i])
+            d, t, c, gq_ref = dev.query_fused(m, q[s].contiguous(), g[s].contiguous(), grad_vertices=gv_ref)
+            torch.cuda.synchronize()
+            assert torch.equal(dist[s], d) and torch.equal(tri[s], t) and torch.equal(gq[s], gq_ref)
+            err = torch.linalg.norm(gvs[i] - gv_ref) / max(torch.linalg.norm(gv_ref).item(), 1e-30)
+            assert err <= 1e-5, (rep, i, err)

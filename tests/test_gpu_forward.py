@@ -115,7 +115,9 @@ def test_small_and_degenerate_meshes(dev):
 
 @pytest.fixture(scope="module")
 def c1(dev):
-    c = gen.config_c1(1000, 1000)
+    # C1's recipe at 128 x 32 segments (16,640 triangles): the full 512 x 128
+    # mesh takes minutes of host preprocessing on its axis clusters
+    c = gen.config_c1(20_000, 20_000, n_seg=128, n_ring=32)
     return c, dev.Mesh(c["V"], c["F"])
 
 
