@@ -56,11 +56,11 @@ def load_traffic(kernel_hash, n_points):
 def bytes_per_query(ctr, n):
     """Algorithmic bytes one query touches (each touch counted once):
     point 12, order 4, seed cell 4, per visited site 32 (position + ranges),
-    adjacency entries 16 each, located site again 32, list entries 24 each
-    (bounding sphere 16 + triangle slot and ell 8), triangle records 48 per
-    exact test, the winner's record 48 + user id 4, outputs 20."""
+    adjacency entries 16 each, located site again 32, list entries 32 each
+    (bounding sphere, first vertex and ell), 32 more per exact test (the two
+    edge vectors and slot), the winner's record 48 + user id 4, outputs 20."""
     per = (12 + 4 + 4 + 32 * ctr["walk_steps"] / n + 16 * ctr["adj_read"] / n + 32
-           + 24 * ctr["list_read"] / n + 48 * ctr["exact_tests"] / n + 52 + 20)
+           + 32 * ctr["list_read"] / n + 32 * ctr["exact_tests"] / n + 52 + 20)
     return per
 
 
@@ -132,7 +132,7 @@ def main():
            torch.empty((n, 3), dtype=torch.float32, device=dev))
 
     def step():
-        p2m.lib().p2m_sort_points(mesh.handle, p2m._ptr(q), n, p2m._ptr(order), p2m._stream(stream))
+        p2m.lib().p2m_sort_points(mesh.handle, p2m._ptr(q), n, p2m._ptr(order), None, p2m._stream(stream))
         ev_mid.record(stream)
         p2m.query_ordered(mesh, q, order, out=out, stream=stream)
 

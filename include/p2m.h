@@ -94,7 +94,12 @@ typedef struct {
 /* Per-handle launch configuration of the query kernels. */
 typedef struct {
     int32_t block_size; /* threads per block: 64..1024, multiple of 64 (default 256) */
-    int32_t reorder;    /* 1: sort queries by seed cell before the search (default 1) */
+    int32_t reorder;    /* 1: sort queries spatially before the search (default 1) */
+    int32_t xcd_groups; /* > 1: give each of this many XCDs (workgroups are dispatched
+                           round-robin over them) a contiguous range of the sorted points;
+                           1 (default, measured faster on MI355X) = plain block order */
+    int32_t sort_bits;  /* sort grid of 2^sort_bits cells per axis (1..8); 0 = automatic,
+                           the finest grid with at most two cells per point */
 } p2m_query_config;
 
 void p2m_default_opts(p2m_build_opts* opts);
@@ -122,14 +127,23 @@ int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_d
 /* The two halves of p2m_query, for callers that sort once and query several
  * times (or time the search kernel alone).
  * p2m_sort_points: writes to d_order (device, n int32) the order in which
- *   p2m_query visits the points: sorted by the Morton rank of each point's
- *   seed-grid cell, points outside the domain box last.  Uses the handle's
- *   workspace (same concurrency rule as p2m_query).
- * p2m_query_ordered: the search of p2m_query, visiting point d_order[j] at
- *   thread j (d_order a permutation of 0..n-1, or NULL for 0..n-1); outputs
- *   are indexed like d_points. */
+ *   p2m_query visits the points: by the Morton code of each point's cell in a
+ *   2^k-per-axis grid over the mesh box x1.25, points outside the domain box
+ *   last; and, if d_sorted_points (device, n x 3, nullable) is given, the
+ *   points themselves in that order.  Uses the handle's workspace (same
+ *   concurrency rule as p2m_query).
+ * p2m_query_ordered: the search of p2m_query, reading the caller's
+ *   d_points and visiting point d_order[j] at thread j (d_order a permutation
+ *   of 0..n-1, or NULL for 0..n-1); outputs are indexed like d_points.
+ *   p2m_query is p2m_sort_points followed by p2m_query_ordered.
+ * p2m_query_sorted: the same search on points already in visiting order
+ *   (d_sorted_points[j] = d_points[d_order[j]], e.g. kept from an earlier
+ *   sort); the outputs for point j go to position d_order[j] (or j if
+ *   d_order is NULL). */
 int32_t p2m_sort_points(p2m_handle h, const float* d_points, int64_t n, int32_t* d_order,
-                        void* stream);
+                        float* d_sorted_points, void* stream);
+int32_t p2m_query_sorted(p2m_handle h, const float* d_sorted_points, const int32_t* d_order, int64_t n,
+                         float* d_out_dist, int32_t* d_out_tri, float* d_out_closest, void* stream);
 int32_t p2m_query_ordered(p2m_handle h, const float* d_points, const int32_t* d_order, int64_t n,
                           float* d_out_dist, int32_t* d_out_tri, float* d_out_closest,
                           void* stream);

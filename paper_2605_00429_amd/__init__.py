@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import P2MError, check, lib
 
 __all__ = ["Mesh", "Batch", "distance", "query", "query_backward", "query_fused",
-           "query_counters", "sort_points", "query_ordered", "P2MError", "build_opts"]
+           "query_counters", "sort_points", "query_sorted", "query_ordered", "P2MError", "build_opts"]
 
 
 def build_opts(**kw):
@@ -112,12 +112,15 @@ class Mesh:
     def query_config(self):
         c = _lib.p2m_query_config()
         check(lib().p2m_get_query_config(self.handle, ctypes.byref(c)))
-        return {"block_size": c.block_size, "reorder": c.reorder}
+        return {"block_size": c.block_size, "reorder": c.reorder, "xcd_groups": c.xcd_groups,
+                "sort_bits": c.sort_bits}
 
-    def set_query_config(self, block_size=None, reorder=None):
+    def set_query_config(self, block_size=None, reorder=None, xcd_groups=None, sort_bits=None):
         cur = self.query_config()
         c = _lib.p2m_query_config(block_size if block_size is not None else cur["block_size"],
-                                  int(reorder) if reorder is not None else cur["reorder"])
+                                  int(reorder) if reorder is not None else cur["reorder"],
+                                  xcd_groups if xcd_groups is not None else cur["xcd_groups"],
+                                  sort_bits if sort_bits is not None else cur["sort_bits"])
         check(lib().p2m_set_query_config(self.handle, ctypes.byref(c)))
 
     def host_sites(self):
@@ -189,13 +192,32 @@ def query(mesh, points, want_tri=True, want_closest=True, stream=None):
     return dist, tri, closest
 
 
-def sort_points(mesh, points, stream=None):
-    """The order (int32 permutation) in which ``query`` visits the points."""
+def sort_points(mesh, points, want_sorted=False, stream=None):
+    """The order (int32 permutation) in which ``query`` visits the points, and
+    with ``want_sorted`` also the points in that order: ``(order, sorted)``."""
     import torch
     p = _check_points(mesh, points)
     order = torch.empty(p.shape[0], dtype=torch.int32, device=p.device)
-    check(lib().p2m_sort_points(mesh.handle, _ptr(p), p.shape[0], _ptr(order), _stream(stream)))
-    return order
+    sp = torch.empty_like(p) if want_sorted else None
+    check(lib().p2m_sort_points(mesh.handle, _ptr(p), p.shape[0], _ptr(order), _ptr(sp), _stream(stream)))
+    return (order, sp) if want_sorted else order
+
+
+def query_sorted(mesh, sorted_points, order, out=None, stream=None):
+    """The search half of ``query`` on points already in visiting order;
+    outputs land at ``order`` positions.  ``out`` may supply preallocated
+    ``(dist, tri, closest)`` tensors."""
+    import torch
+    p = _check_points(mesh, sorted_points)
+    n = p.shape[0]
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float32, device=p.device),
+               torch.empty(n, dtype=torch.int32, device=p.device),
+               torch.empty((n, 3), dtype=torch.float32, device=p.device))
+    dist, tri, closest = out
+    check(lib().p2m_query_sorted(mesh.handle, _ptr(p), _ptr(order), n, _ptr(dist), _ptr(tri), _ptr(closest),
+                                 _stream(stream)))
+    return dist, tri, closest
 
 
 def query_ordered(mesh, points, order, out=None, stream=None):

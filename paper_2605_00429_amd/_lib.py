@@ -61,7 +61,8 @@ class p2m_stats(ctypes.Structure):
 
 
 class p2m_query_config(ctypes.Structure):
-    _fields_ = [("block_size", ctypes.c_int32), ("reorder", ctypes.c_int32)]
+    _fields_ = [("block_size", ctypes.c_int32), ("reorder", ctypes.c_int32), ("xcd_groups", ctypes.c_int32),
+                ("sort_bits", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -81,7 +82,8 @@ SIGNATURES = {
     "p2m_get_query_config": (_I32, [_VP, ctypes.POINTER(p2m_query_config)]),
     "p2m_set_query_config": (_I32, [_VP, ctypes.POINTER(p2m_query_config)]),
     "p2m_query_counters": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP]),
-    "p2m_sort_points": (_I32, [_VP, _VP, _I64, _VP, _VP]),
+    "p2m_sort_points": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP]),
+    "p2m_query_sorted": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP]),
     "p2m_query_ordered": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP]),
     "p2m_host_sites": (_I32, [_VP, _VP, _VP]),
     "p2m_host_site_of_vertex": (_I32, [_VP, _VP]),

@@ -130,7 +130,7 @@ struct p2m_batch_ {
         std::vector<const int32_t*> perms(meshes.size(), nullptr);
         for (size_t i = 0; i < meshes.size(); ++i) {
             if (counts[i] == 0) continue;
-            e = p2m::launch_reorder(p2m::handle_devmesh(meshes[i]), args.q + 3 * q_off[i], counts[i],
+            e = p2m::launch_reorder(p2m::handle_devmesh(meshes[i]), args.q + 3 * q_off[i], counts[i], 0,
                                     (char*)ws + ws_off[i], &perms[i], st);
             if (e != hipSuccess) return e;
         }
@@ -224,7 +224,7 @@ int32_t p2m_batch_create(const p2m_handle* meshes, int32_t n_meshes, const int64
     b->ws_off.resize(n_meshes);
     for (int i = 0; i < n_meshes; ++i) {
         b->ws_off[i] = ws_total;
-        ws_total += (p2m::reorder_workspace_bytes(b->counts[i], dm[i].n_cells) + 255) / 256 * 256;
+        ws_total += (p2m::reorder_workspace_bytes(b->counts[i], 0) + 255) / 256 * 256;
     }
     e = hipMalloc(&b->d_meshes, sizeof(p2m::DevMesh) * n_meshes);
     if (e == hipSuccess) e = hipMalloc(&b->d_qoff, sizeof(int64_t) * (n_meshes + 1));
@@ -239,7 +239,8 @@ int32_t p2m_batch_create(const p2m_handle* meshes, int32_t n_meshes, const int64
     // Each mesh's sorted order lands at the same place in its workspace on every call.
     std::vector<int32_t*> perm(n_meshes, nullptr);
     for (int i = 0; i < n_meshes; ++i)
-        if (b->counts[i] > 0) perm[i] = (int32_t*)((char*)b->ws + b->ws_off[i]) + 2 * b->counts[i];
+        if (b->counts[i] > 0)
+            perm[i] = (int32_t*)p2m::reorder_perm_location((char*)b->ws + b->ws_off[i], b->counts[i], 0);
     e = hipMemcpy(b->d_meshes, dm.data(), sizeof(p2m::DevMesh) * n_meshes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_qoff, b->q_off.data(), sizeof(int64_t) * (n_meshes + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_perm, perm.data(), sizeof(int32_t*) * n_meshes, hipMemcpyHostToDevice);

@@ -50,7 +50,7 @@ struct p2m_handle_ {
     p2m::DevMesh dm{};
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
-    p2m_query_config cfg{256, 1};
+    p2m_query_config cfg{256, 1, 1, 0};
     void* ws = nullptr;
     size_t ws_bytes = 0;
 
@@ -83,11 +83,10 @@ struct p2m_handle_ {
     {
         using namespace p2m;
         const HostStructure& h = H;
-        dm.site_xyz = upload<float4>(h.site_xyz.data(), h.site_xyz.size() * 4);
-        dm.site_rng = upload<int4>(h.site_rng.data(), h.site_rng.size() * 4);
+        static_assert(sizeof(SiteRec) == 32 && sizeof(ListRec) == 64, "device record layout");
+        dm.site_rec = upload<float4>(h.site_rec.data(), h.site_rec.size() * sizeof(SiteRec));
         dm.adj = upload<float4>(h.adj.data(), h.adj.size() * 4);
-        dm.list_sph = upload<float4>(h.list_sph.data(), h.list_sph.size() * 4);
-        dm.list_aux = upload<int2>(h.list_aux.data(), h.list_aux.size() * 4);
+        dm.list_rec = upload<float4>(h.list_rec.data(), h.list_rec.size() * sizeof(ListRec));
         dm.tri_rec = upload<float4>(h.tri_rec.data(), h.tri_rec.size() * 4);
         dm.tri_user = upload<int32_t>(h.tri_user.data(), h.tri_user.size() * 4);
         dm.tri_vid = upload<int4>(h.tri_vid.data(), h.tri_vid.size() * 4);
@@ -95,26 +94,6 @@ struct p2m_handle_ {
         for (int64_t i = 0; i < h.n_triangles; ++i) slot[h.tri_user[i]] = (int32_t)i;
         dm.tri_slot = upload<int32_t>(slot.data(), slot.size() * 4);
         dm.seed = upload<int32_t>(h.seed.data(), h.seed.size() * 4);
-        // Morton rank of every seed cell, for sorting queries
-        const int64_t nc = (int64_t)h.seed.size();
-        std::vector<std::pair<uint64_t, int32_t>> mk(nc);
-        auto spread = [](uint64_t x) {
-            x &= 0x1fffff;
-            x = (x | x << 32) & 0x1f00000000ffffULL;
-            x = (x | x << 16) & 0x1f0000ff0000ffULL;
-            x = (x | x << 8) & 0x100f00f00f00f00fULL;
-            x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
-            x = (x | x << 2) & 0x1249249249249249ULL;
-            return x;
-        };
-        for (int64_t c = 0; c < nc; ++c) {
-            const int64_t ix = c % h.gdim[0], iy = (c / h.gdim[0]) % h.gdim[1], iz = c / ((int64_t)h.gdim[0] * h.gdim[1]);
-            mk[c] = {spread(ix) | (spread(iy) << 1) | (spread(iz) << 2), (int32_t)c};
-        }
-        std::sort(mk.begin(), mk.end());
-        std::vector<int32_t> rank(nc);
-        for (int64_t r = 0; r < nc; ++r) rank[mk[r].second] = (int32_t)r;
-        dm.cell_rank = upload<int32_t>(rank.data(), rank.size() * 4);
         dm.bvh = upload<float4>(h.bvh.data(), h.bvh.size() * 4);
         for (int k = 0; k < 3; ++k) {
             dm.gdim[k] = h.gdim[k];
@@ -126,7 +105,6 @@ struct p2m_handle_ {
         dm.n_sites = h.n_sites;
         dm.n_tris = (int32_t)h.n_triangles;
         dm.n_vertices = (int32_t)h.n_vertices;
-        dm.n_cells = (int32_t)nc;
     }
 
     // Grows the query workspace; waits for earlier work on `st` first.
@@ -239,6 +217,10 @@ int32_t p2m_set_query_config(p2m_handle h, const p2m_query_config* c)
     if (!h || !c) return fail(P2M_ERR_INVALID_ARG, "null handle or config");
     if (c->block_size < 64 || c->block_size > 1024 || c->block_size % 64 != 0)
         return fail(P2M_ERR_INVALID_ARG, "block_size must be a multiple of 64 in [64, 1024]");
+    if (c->xcd_groups < 1 || c->xcd_groups > 64)
+        return fail(P2M_ERR_INVALID_ARG, "xcd_groups must be in [1, 64]");
+    if (c->sort_bits < 0 || c->sort_bits > 8)
+        return fail(P2M_ERR_INVALID_ARG, "sort_bits must be in [0, 8]");
     h->cfg = *c;
     return P2M_OK;
 }
@@ -266,11 +248,13 @@ static int32_t query_common(p2m_handle h, const float* q, int64_t n, float* dist
     a.grad_q = gq;
     a.grad_v = gv;
     a.ctr = ctr;
+    a.xcds = h->cfg.xcd_groups;
     if (h->cfg.reorder) {
-        const size_t need = p2m::reorder_workspace_bytes(n, h->dm.n_cells);
-        int32_t rc = h->ensure_ws(need, st);
+        // The search gathers each point through the order: measured faster
+        // than having the sort also write the points in visiting order.
+        int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st);
         if (rc != P2M_OK) return rc;
-        hipError_t e = p2m::launch_reorder(h->dm, q, n, h->ws, &a.perm, st);
+        hipError_t e = p2m::launch_reorder(h->dm, q, n, h->cfg.sort_bits, h->ws, &a.perm, st);
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
     }
     hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, fused, ctr != nullptr, st);
@@ -285,7 +269,8 @@ int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_d
                         nullptr, false, stream);
 }
 
-int32_t p2m_sort_points(p2m_handle h, const float* d_points, int64_t n, int32_t* d_order, void* stream)
+int32_t p2m_sort_points(p2m_handle h, const float* d_points, int64_t n, int32_t* d_order,
+                        float* d_sorted_points, void* stream)
 {
     if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
     if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
@@ -295,10 +280,10 @@ int32_t p2m_sort_points(p2m_handle h, const float* d_points, int64_t n, int32_t*
     if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
     DeviceGuard dg(h->device);
     hipStream_t st = (hipStream_t)stream;
-    int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->dm.n_cells), st);
+    int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st);
     if (rc != P2M_OK) return rc;
     const int32_t* perm = nullptr;
-    hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->ws, &perm, st);
+    hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->cfg.sort_bits, h->ws, &perm, st, d_sorted_points);
     if (e == hipSuccess) e = hipMemcpyAsync(d_order, perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "sort launch");
     return P2M_OK;
@@ -321,6 +306,31 @@ int32_t p2m_query_ordered(p2m_handle h, const float* d_points, const int32_t* d_
     a.dist = d_out_dist;
     a.tri = d_out_tri;
     a.closest = d_out_closest;
+    a.xcds = h->cfg.xcd_groups;
+    hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, false, false, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return P2M_OK;
+}
+
+int32_t p2m_query_sorted(p2m_handle h, const float* d_sorted_points, const int32_t* d_order, int64_t n,
+                         float* d_out_dist, int32_t* d_out_tri, float* d_out_closest, void* stream)
+{
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (n == 0) return P2M_OK;
+    if (!d_sorted_points || !d_out_dist) return fail(P2M_ERR_INVALID_ARG, "null points or distance output");
+    if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
+    DeviceGuard dg(h->device);
+    p2m::FwdArgs a{};
+    a.q = d_sorted_points;
+    a.q_sorted = 1;
+    a.perm = d_order;
+    a.n = n;
+    a.dist = d_out_dist;
+    a.tri = d_out_tri;
+    a.closest = d_out_closest;
+    a.xcds = h->cfg.xcd_groups;
     hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, false, false, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return P2M_OK;
@@ -367,7 +377,7 @@ int32_t p2m_host_sites(p2m_handle h, float* out_xyz, uint8_t* out_is_aux)
 {
     if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
     for (int32_t s = 0; s < h->H.n_sites; ++s) {
-        if (out_xyz) std::memcpy(out_xyz + 3 * (int64_t)s, &h->H.site_xyz[4 * (int64_t)s], 12);
+        if (out_xyz) std::memcpy(out_xyz + 3 * (int64_t)s, &h->H.site_rec[s].x, 12);
         if (out_is_aux) out_is_aux[s] = h->H.site_is_aux[s];
     }
     return P2M_OK;
@@ -384,10 +394,10 @@ int32_t p2m_host_list(p2m_handle h, int64_t site, int32_t* out_tris, int64_t cap
 {
     if (!h || !len || cap < 0) return fail(P2M_ERR_INVALID_ARG, "null handle or length");
     if (site < 0 || site >= h->H.n_sites) return fail(P2M_ERR_INVALID_ARG, "site out of range");
-    const int32_t b = h->H.site_rng[4 * site + 2], e = h->H.site_rng[4 * site + 3];
+    const int32_t b = h->H.site_rec[site].list_begin, e = h->H.site_rec[site].list_end;
     *len = e - b;
     for (int64_t k = 0; k < std::min<int64_t>(cap, e - b) && out_tris; ++k)
-        out_tris[k] = h->H.tri_user[h->H.list_aux[2 * (b + k)]];
+        out_tris[k] = h->H.list_rec[b + k].tri;
     return P2M_OK;
 }
 
@@ -395,7 +405,7 @@ int32_t p2m_host_neighbors(p2m_handle h, int64_t site, int32_t* out, int64_t cap
 {
     if (!h || !len || cap < 0) return fail(P2M_ERR_INVALID_ARG, "null handle or length");
     if (site < 0 || site >= h->H.n_sites) return fail(P2M_ERR_INVALID_ARG, "site out of range");
-    const int32_t b = h->H.site_rng[4 * site], e = h->H.site_rng[4 * site + 1];
+    const int32_t b = h->H.site_rec[site].adj_begin, e = h->H.site_rec[site].adj_end;
     *len = e - b;
     for (int64_t k = 0; k < std::min<int64_t>(cap, e - b) && out; ++k) {
         int32_t id;
@@ -422,11 +432,12 @@ int32_t p2m_host_locate(p2m_handle h, const float* pts, int64_t n, int32_t* out_
         };
         int s = H.seed[((int64_t)cell(qz, 2) * H.gdim[1] + cell(qy, 1)) * H.gdim[0] + cell(qx, 0)];
         for (int it = 0; it < 4096; ++it) {
-            const float* sp = &H.site_xyz[4 * (int64_t)s];
+            const p2m::SiteRec& sr = H.site_rec[s];
+            const float sp[3] = {sr.x, sr.y, sr.z};
             const double wx = (double)qx - sp[0], wy = (double)qy - sp[1], wz = (double)qz - sp[2];
             double best = 0.0;
             int nxt = -1;
-            for (int32_t k = H.site_rng[4 * (int64_t)s]; k < H.site_rng[4 * (int64_t)s + 1]; ++k) {
+            for (int32_t k = sr.adj_begin; k < sr.adj_end; ++k) {
                 const float* a = &H.adj[4 * (int64_t)k];
                 const double dx = (double)a[0] - sp[0], dy = (double)a[1] - sp[1], dz = (double)a[2] - sp[2];
                 const double val = wx * dx + wy * dy + wz * dz - 0.5 * (dx * dx + dy * dy + dz * dz);

@@ -9,31 +9,29 @@ namespace p2m {
 // Read-only search structure of one mesh in device memory (see build.h for
 // the meaning of each array).  Passed to kernels by value.
 struct DevMesh {
-    const float4* site_xyz;  // n_sites
-    const int4* site_rng;    // n_sites: adj begin, adj end, list begin, list end
+    const float4* site_rec;  // 2 per site: (x, y, z, 0), int4 (adj begin, end, list begin, end)
     const float4* adj;       // neighbour xyz + id bits
-    const float4* list_sph;  // bounding sphere per list entry
-    const int2* list_aux;    // triangle slot, ell bits
+    const float4* list_rec;  // 4 per list entry: (c, r), (a, ell), (e1, e1.e2), (e2, caller triangle id bits)
     const float4* tri_rec;   // 3 per slot: (a, |e1|^2), (e1, e1.e2), (e2, |e2|^2)
     const int32_t* tri_user; // slot -> caller triangle id
-    const int4* tri_vid;     // slot -> caller vertex ids
+    const int4* tri_vid;     // caller triangle id -> caller vertex ids
     const int32_t* tri_slot; // caller triangle id -> slot
     const int32_t* seed;     // seed grid (x fastest)
-    const int32_t* cell_rank;// seed cell -> rank in Morton order (query sorting)
     const float4* bvh;       // 2 per node
     int32_t gdim[3];
     float gorg[3];
     float ginv;              // 1 / seed cell size
     float dlo[3], dhi[3];    // domain box
-    int32_t n_sites, n_tris, n_vertices, n_cells;
+    int32_t n_sites, n_tris, n_vertices;
 };
 
 // Counter slots of the instrumented forward.
 enum { CTR_WALK_STEPS = 0, CTR_ADJ_READ, CTR_LIST_READ, CTR_EXACT, CTR_FALLBACK, CTR_LIST_LEN, CTR_N };
 
 struct FwdArgs {
-    const float* q;          // n x 3
-    const int32_t* perm;     // optional processing order
+    const float* q;          // n x 3: caller order, or visiting order when q_sorted
+    const int32_t* perm;     // optional processing order (output positions)
+    int32_t q_sorted;        // q[j] is the j-th point visited (already permuted)
     int64_t n;
     float* dist;
     int32_t* tri;            // nullable
@@ -42,6 +40,7 @@ struct FwdArgs {
     float* grad_q;           // fused only, nullable
     float* grad_v;           // fused only, nullable
     unsigned long long* ctr; // counters only
+    int32_t xcds;            // blocks are spread over this many XCD groups (see launch_forward)
 };
 
 // Arguments of the persistent batched kernel.  Queries of mesh i occupy
@@ -70,11 +69,16 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
                           hipStream_t st);
 hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* tri,
                            const float* g, float* grad_q, float* grad_v, int block, hipStream_t st);
-// Counting sort of queries by seed cell (Morton rank).  ws must hold
-// workspace_bytes(n, n_cells) bytes; writes the order to *perm_out.
-size_t reorder_workspace_bytes(int64_t n, int32_t n_cells);
-hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, void* ws, const int32_t** perm_out,
-                          hipStream_t st);
+// Radix sort of queries by the Morton code of their cell in a 2^k grid
+// over the seed-grid box (k from n when bits = 0).  ws must hold
+// reorder_workspace_bytes(n) bytes; writes the order to *perm_out.
+// bits = 0 picks the resolution from n.
+size_t reorder_workspace_bytes(int64_t n, int bits);
+// sorted_q (nullable, n x 3): also receives the points in the sorted order.
+hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, int bits, void* ws,
+                          const int32_t** perm_out, hipStream_t st, float* sorted_q = nullptr);
+// Where launch_reorder leaves the order inside ws (fixed for given n, bits).
+const int32_t* reorder_perm_location(void* ws, int64_t n, int bits);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 
 }  // namespace p2m

@@ -55,13 +55,6 @@ float round_up(double x)
     return f;
 }
 
-int32_t fbits(float f)
-{
-    int32_t i;
-    std::memcpy(&i, &f, 4);
-    return i;
-}
-
 float ibits(int32_t i)
 {
     float f;
@@ -580,10 +573,31 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     std::vector<int32_t> new_id(nS);
     for (int32_t i = 0; i < nS; ++i) new_id[sorder[i]] = i;
 
+    // triangle records in slot order
+    H.tri_rec.resize(12 * (size_t)nT);
+    H.tri_user.resize(nT);
+    H.tri_vid.resize(4 * (size_t)nT);
+    for (int64_t i = 0; i < nT; ++i) {
+        const int32_t t = torder[i];
+        const d3 a = T[3 * t], b = T[3 * t + 1], c = T[3 * t + 2];
+        const float e1x = (float)(b.x - a.x), e1y = (float)(b.y - a.y), e1z = (float)(b.z - a.z);
+        const float e2x = (float)(c.x - a.x), e2y = (float)(c.y - a.y), e2z = (float)(c.z - a.z);
+        const double g11 = (double)e1x * e1x + (double)e1y * e1y + (double)e1z * e1z;
+        const double g12 = (double)e1x * e2x + (double)e1y * e2y + (double)e1z * e2z;
+        const double g22 = (double)e2x * e2x + (double)e2y * e2y + (double)e2z * e2z;
+        float* r = &H.tri_rec[12 * i];
+        r[0] = (float)a.x; r[1] = (float)a.y; r[2] = (float)a.z; r[3] = (float)g11;
+        r[4] = e1x; r[5] = e1y; r[6] = e1z; r[7] = (float)g12;
+        r[8] = e2x; r[9] = e2y; r[10] = e2z; r[11] = (float)g22;
+        H.tri_user[i] = t;
+        H.tri_vid[4 * (size_t)t] = mesh.triangles[3 * t];
+        H.tri_vid[4 * (size_t)t + 1] = mesh.triangles[3 * t + 1];
+        H.tri_vid[4 * (size_t)t + 2] = mesh.triangles[3 * t + 2];
+        H.tri_vid[4 * (size_t)t + 3] = 0;
+    }
     H.n_sites = nS;
     H.n_aux = nS - nVS;
-    H.site_xyz.assign(4 * (size_t)nS, 0.f);
-    H.site_rng.assign(4 * (size_t)nS, 0);
+    H.site_rec.assign(nS, SiteRec{});
     H.site_is_aux.assign(nS, 0);
     int64_t adj_nnz = 0, list_nnz = 0, adj_max = 0, list_max = 0;
     for (int32_t s = 0; s < nS; ++s) {
@@ -595,8 +609,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     if (adj_nnz > std::numeric_limits<int32_t>::max() || list_nnz > std::numeric_limits<int32_t>::max())
         throw Error(P2M_ERR_OOM, "interception lists exceed 2^31 entries");
     H.adj.resize(4 * (size_t)adj_nnz);
-    H.list_sph.resize(4 * (size_t)list_nnz);
-    H.list_aux.resize(2 * (size_t)list_nnz);
+    H.list_rec.resize((size_t)list_nnz);
     std::vector<int64_t> adj_off(nS + 1, 0), list_off(nS + 1, 0);
     for (int32_t i = 0; i < nS; ++i) {
         const int32_t s = sorder[i];
@@ -606,14 +619,16 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     parallel_for(nS, nth, [&](int64_t i, int) {
         const int32_t s = sorder[i];
         const float sx = (float)P[s].x, sy = (float)P[s].y, sz = (float)P[s].z;
-        H.site_xyz[4 * i] = sx;
-        H.site_xyz[4 * i + 1] = sy;
-        H.site_xyz[4 * i + 2] = sz;
+        SiteRec& sr = H.site_rec[i];
+        sr.x = sx;
+        sr.y = sy;
+        sr.z = sz;
+        sr.pad = 0.f;
+        sr.adj_begin = (int32_t)adj_off[i];
+        sr.adj_end = (int32_t)adj_off[i + 1];
+        sr.list_begin = (int32_t)list_off[i];
+        sr.list_end = (int32_t)list_off[i + 1];
         H.site_is_aux[i] = is_aux[s];
-        H.site_rng[4 * i] = (int32_t)adj_off[i];
-        H.site_rng[4 * i + 1] = (int32_t)adj_off[i + 1];
-        H.site_rng[4 * i + 2] = (int32_t)list_off[i];
-        H.site_rng[4 * i + 3] = (int32_t)list_off[i + 1];
         std::vector<int32_t> nb(nbr[s].size());
         for (size_t k = 0; k < nb.size(); ++k) nb[k] = new_id[nbr[s][k]];
         std::sort(nb.begin(), nb.end());
@@ -636,37 +651,31 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         std::sort(ent.begin(), ent.end());
         for (size_t k = 0; k < ent.size(); ++k) {
             const int64_t e = list_off[i] + (int64_t)k;
-            const int32_t t = torder[ent[k].second];
-            std::memcpy(&H.list_sph[4 * e], &sph[4 * t], 16);
-            H.list_aux[2 * e] = ent[k].second;
-            H.list_aux[2 * e + 1] = fbits(ent[k].first);
+            const int32_t slot = ent[k].second;
+            const int32_t t = torder[slot];
+            const float* tr = &H.tri_rec[12 * (size_t)slot];
+            ListRec& L = H.list_rec[e];
+            L.cx = sph[4 * t];
+            L.cy = sph[4 * t + 1];
+            L.cz = sph[4 * t + 2];
+            L.r = sph[4 * t + 3];
+            L.ax = tr[0];
+            L.ay = tr[1];
+            L.az = tr[2];
+            L.ell = ent[k].first;
+            L.e1x = tr[4];
+            L.e1y = tr[5];
+            L.e1z = tr[6];
+            L.g12 = tr[7];
+            L.e2x = tr[8];
+            L.e2y = tr[9];
+            L.e2z = tr[10];
+            L.tri = t;
         }
     }, 256);
     for (int64_t v = 0; v < nV; ++v)
         if (H.site_of_vertex[v] >= 0) H.site_of_vertex[v] = new_id[H.site_of_vertex[v]];
 
-    // triangle records in slot order
-    H.tri_rec.resize(12 * (size_t)nT);
-    H.tri_user.resize(nT);
-    H.tri_vid.resize(4 * (size_t)nT);
-    for (int64_t i = 0; i < nT; ++i) {
-        const int32_t t = torder[i];
-        const d3 a = T[3 * t], b = T[3 * t + 1], c = T[3 * t + 2];
-        const float e1x = (float)(b.x - a.x), e1y = (float)(b.y - a.y), e1z = (float)(b.z - a.z);
-        const float e2x = (float)(c.x - a.x), e2y = (float)(c.y - a.y), e2z = (float)(c.z - a.z);
-        const double g11 = (double)e1x * e1x + (double)e1y * e1y + (double)e1z * e1z;
-        const double g12 = (double)e1x * e2x + (double)e1y * e2y + (double)e1z * e2z;
-        const double g22 = (double)e2x * e2x + (double)e2y * e2y + (double)e2z * e2z;
-        float* r = &H.tri_rec[12 * i];
-        r[0] = (float)a.x; r[1] = (float)a.y; r[2] = (float)a.z; r[3] = (float)g11;
-        r[4] = e1x; r[5] = e1y; r[6] = e1z; r[7] = (float)g12;
-        r[8] = e2x; r[9] = e2y; r[10] = e2z; r[11] = (float)g22;
-        H.tri_user[i] = t;
-        H.tri_vid[4 * i] = mesh.triangles[3 * t];
-        H.tri_vid[4 * i + 1] = mesh.triangles[3 * t + 1];
-        H.tri_vid[4 * i + 2] = mesh.triangles[3 * t + 2];
-        H.tri_vid[4 * i + 3] = 0;
-    }
     // fallback BVH nodes
     const auto& nodes = bvh.nodes();
     H.bvh.resize(8 * nodes.size());

@@ -11,25 +11,39 @@
 
 namespace p2m {
 
+// One site: position and the ranges of its adjacency and list entries.
+struct SiteRec {
+    float x, y, z, pad;
+    int32_t adj_begin, adj_end, list_begin, list_end;
+};
+
+// One interception-list entry (64 B): the triangle's bounding sphere, its
+// record for the exact test (a, e1, e2 and e1.e2; |e1|^2 and |e2|^2 are
+// recomputed), ell = |s - c| - r rounded down, and the caller's triangle id.
+struct ListRec {
+    float cx, cy, cz, r;
+    float ax, ay, az, ell;
+    float e1x, e1y, e1z, g12;
+    float e2x, e2y, e2z;
+    int32_t tri;
+};
+
 struct HostStructure {
     int64_t n_vertices = 0, n_triangles = 0;
     double diag = 0;  // mesh AABB diagonal
 
-    // Sites in device order.  site_xyz: x, y, z, 0.  site_rng: adjacency
-    // begin/end and list begin/end.
+    // Sites in device order.
     int32_t n_sites = 0, n_aux = 0;
-    std::vector<float> site_xyz;
-    std::vector<int32_t> site_rng;
+    std::vector<SiteRec> site_rec;
     std::vector<uint8_t> site_is_aux;
     // Adjacency entries: neighbour x, y, z and its site id (int bits).
     std::vector<float> adj;
-    // List entries: bounding sphere (cx, cy, cz, r) and (triangle slot, ell bits).
-    std::vector<float> list_sph;
-    std::vector<int32_t> list_aux;
+    // Interception-list entries, each site's list sorted by ell.
+    std::vector<ListRec> list_rec;
     // Triangles in slot order (BVH leaf order): v0, |e1|^2 | e1, e1.e2 | e2, |e2|^2.
     std::vector<float> tri_rec;
     std::vector<int32_t> tri_user;  // slot -> caller's triangle id
-    std::vector<int32_t> tri_vid;   // slot -> caller's vertex ids a, b, c, 0
+    std::vector<int32_t> tri_vid;   // caller triangle id -> caller's vertex ids a, b, c, 0
     // Seed grid: exact nearest site of every cell centre.
     std::vector<int32_t> seed;
     int32_t gdim[3] = {0, 0, 0};

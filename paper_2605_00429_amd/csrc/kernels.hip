@@ -2,12 +2,11 @@
 //
 // Query (Sec. 3.4 of the paper), one lane per point:
 //   1. Cell Locate: start at the exact nearest site of the point's seed-grid
-//      cell and walk the Delaunay graph, moving to the neighbour that is
-//      closest to q, until no neighbour is closer.  On the Delaunay graph a
-//      local minimum is the nearest site.  The bisector predicate
-//      (q - s).(t - s) > |t - s|^2 / 2 is evaluated in FP64 (half rate on
-//      CDNA4 vector units), which makes the located site exact up to 1e-16
-//      relative, so the lists need no query-dependent inflation.
+//      cell and walk the Delaunay graph, moving to a neighbour closer to q
+//      until none is closer.  On the Delaunay graph a local minimum is the
+//      nearest site.  The bisector predicate (q - s).(t - s) > |t - s|^2 / 2
+//      is decided exactly: in FP32 when its rounding bound allows, else in
+//      FP64, so the lists need no query-dependent inflation.
 //   2. List Search: scan the site's interception list (sorted by
 //      ell = |s - c| - r), skip an entry when |q - c| - r >= d_min
 //      (bounding-sphere pruning), stop when ell - |q - s| >= d_min (no later
@@ -33,11 +32,19 @@ namespace {
 constexpr float kInf = __builtin_huge_valf();
 constexpr int kWalkCap = 4096;
 
-// Closest point of the triangle record (a, e1, e2 with Gram entries) to q.
-// Returns the squared distance and the barycentric weights (v, w) of b and c.
-__device__ __forceinline__ float closest_point(const float3 q, const float4 r0, const float4 r1,
-                                               const float4 r2, float& v, float& w)
+// Closest point of the triangle record (a, e1, e2 with Gram entries) to q,
+// by classifying q against the triangle's vertex, edge and face regions
+// (Ericson, Real-Time Collision Detection, Sec. 5.1.5).  The region tests
+// are evaluated for all regions and resolved with selects, so lanes in
+// different regions do not diverge; reciprocals use the 1-ulp hardware
+// instruction.  Returns the squared distance and the barycentric weights
+// (v, w) of b and c.
+__device__ __forceinline__ float closest_point(const float3 q, const float3 a, const float3 e1, const float3 e2,
+                                               const float g12, float& v, float& w)
 {
+    const float4 r0 = make_float4(a.x, a.y, a.z, e1.x * e1.x + e1.y * e1.y + e1.z * e1.z);
+    const float4 r1 = make_float4(e1.x, e1.y, e1.z, g12);
+    const float4 r2 = make_float4(e2.x, e2.y, e2.z, e2.x * e2.x + e2.y * e2.y + e2.z * e2.z);
     const float apx = q.x - r0.x, apy = q.y - r0.y, apz = q.z - r0.z;
     const float d1 = r1.x * apx + r1.y * apy + r1.z * apz;  // e1 . (q - a)
     const float d2 = r2.x * apx + r2.y * apy + r2.z * apz;  // e2 . (q - a)
@@ -48,45 +55,64 @@ __device__ __forceinline__ float closest_point(const float3 q, const float4 r0, 
     const float vc = d1 * d4 - d3 * d2;
     const float vb = d5 * d2 - d1 * d6;
     const float va = d3 * d6 - d5 * d4;
-    if (d1 <= 0.f && d2 <= 0.f) {
-        v = 0.f; w = 0.f;
-    } else if (d3 >= 0.f && d4 <= d3) {
-        v = 1.f; w = 0.f;
-    } else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
-        v = d1 / (d1 - d3); w = 0.f;
-    } else if (d6 >= 0.f && d5 <= d6) {
-        v = 0.f; w = 1.f;
-    } else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {
-        v = 0.f; w = d2 / (d2 - d6);
-    } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
-        w = (d4 - d3) / ((d4 - d3) + (d5 - d6)); v = 1.f - w;
-    } else {
-        const float den = va + vb + vc;
-        if (den > 0.f && den < kInf) {
-            v = vb / den; w = vc / den;
-        } else {
-            // zero-area triangle: best of its three edges
-            const float g11 = r0.w, g12 = r1.w, g22 = r2.w;
-            float t0 = g11 > 0.f ? fminf(fmaxf(d1 / g11, 0.f), 1.f) : 0.f;      // a + t e1
-            float t1 = g22 > 0.f ? fminf(fmaxf(d2 / g22, 0.f), 1.f) : 0.f;      // a + t e2
-            const float g33 = g11 - 2.f * g12 + g22;                            // |e2 - e1|^2
-            float t2 = g33 > 0.f ? fminf(fmaxf((d2 - d1 - g12 + g11) / g33, 0.f), 1.f) : 0.f;  // b + t (c - b)
-            auto dist2 = [&](float vv, float ww) {
-                const float rx = apx - vv * r1.x - ww * r2.x;
-                const float ry = apy - vv * r1.y - ww * r2.y;
-                const float rz = apz - vv * r1.z - ww * r2.z;
-                return rx * rx + ry * ry + rz * rz;
-            };
-            const float e0 = dist2(t0, 0.f), e1 = dist2(0.f, t1), e2 = dist2(1.f - t2, t2);
-            if (e0 <= e1 && e0 <= e2) { v = t0; w = 0.f; }
-            else if (e1 <= e2) { v = 0.f; w = t1; }
-            else { v = 1.f - t2; w = t2; }
-        }
+    const float den = va + vb + vc;
+    const float e43 = d4 - d3, e56 = d5 - d6;
+    // face region, then each edge / vertex region in increasing priority
+    const float inv = __builtin_amdgcn_rcpf(den);
+    float vv = vb * inv, ww = vc * inv;
+    bool face = true;
+    if (va <= 0.f && e43 >= 0.f && e56 >= 0.f) {  // edge bc
+        const float t = e43 * __builtin_amdgcn_rcpf(e43 + e56);
+        vv = 1.f - t; ww = t; face = false;
     }
-    const float rx = apx - v * r1.x - w * r2.x;
-    const float ry = apy - v * r1.y - w * r2.y;
-    const float rz = apz - v * r1.z - w * r2.z;
+    if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {    // edge ca
+        vv = 0.f; ww = d2 * __builtin_amdgcn_rcpf(d2 - d6); face = false;
+    }
+    if (d6 >= 0.f && d5 <= d6) {                  // vertex c
+        vv = 0.f; ww = 1.f; face = false;
+    }
+    if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {    // edge ab
+        vv = d1 * __builtin_amdgcn_rcpf(d1 - d3); ww = 0.f; face = false;
+    }
+    if (d3 >= 0.f && d4 <= d3) {                  // vertex b
+        vv = 1.f; ww = 0.f; face = false;
+    }
+    if (d1 <= 0.f && d2 <= 0.f) {                 // vertex a
+        vv = 0.f; ww = 0.f; face = false;
+    }
+    if (face && !(den > 0.f && den < kInf)) {
+        // zero-area triangle: best of its three edges (rare)
+        const float g11 = r0.w, g12 = r1.w, g22 = r2.w;
+        const float t0 = g11 > 0.f ? fminf(fmaxf(d1 / g11, 0.f), 1.f) : 0.f;      // a + t e1
+        const float t1 = g22 > 0.f ? fminf(fmaxf(d2 / g22, 0.f), 1.f) : 0.f;      // a + t e2
+        const float g33 = g11 - 2.f * g12 + g22;                                  // |e2 - e1|^2
+        const float t2 = g33 > 0.f ? fminf(fmaxf((d2 - d1 - g12 + g11) / g33, 0.f), 1.f) : 0.f;
+        auto dist2 = [&](float a1, float a2) {
+            const float rx = apx - a1 * r1.x - a2 * r2.x;
+            const float ry = apy - a1 * r1.y - a2 * r2.y;
+            const float rz = apz - a1 * r1.z - a2 * r2.z;
+            return rx * rx + ry * ry + rz * rz;
+        };
+        const float e0 = dist2(t0, 0.f), e1 = dist2(0.f, t1), e2 = dist2(1.f - t2, t2);
+        if (e0 <= e1 && e0 <= e2) { vv = t0; ww = 0.f; }
+        else if (e1 <= e2) { vv = 0.f; ww = t1; }
+        else { vv = 1.f - t2; ww = t2; }
+    }
+    v = vv;
+    w = ww;
+    const float rx = apx - vv * r1.x - ww * r2.x;
+    const float ry = apy - vv * r1.y - ww * r2.y;
+    const float rz = apz - vv * r1.z - ww * r2.z;
     return rx * rx + ry * ry + rz * rz;
+}
+
+// The same test on a triangle record (|e1|^2, |e2|^2 in the record are not
+// used: both paths recompute them identically, so results match bitwise).
+__device__ __forceinline__ float closest_point_rec(const float3 q, const float4* r, float& v, float& w)
+{
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+    return closest_point(q, make_float3(r0.x, r0.y, r0.z), make_float3(r1.x, r1.y, r1.z),
+                         make_float3(r2.x, r2.y, r2.z), r1.w, v, w);
 }
 
 __device__ __forceinline__ int seed_cell(const DevMesh& m, const float3 q)
@@ -106,81 +132,139 @@ __device__ __forceinline__ bool in_domain(const DevMesh& m, const float3 q)
            q.z >= m.dlo[2] && q.z <= m.dhi[2];
 }
 
-// Cell Locate: greedy walk on the Delaunay graph from the seed site.
+// FP64 value of the bisector predicate (q - s).(t - s) - |t - s|^2 / 2 for
+// every neighbour t of s; the best positive one, or -1.
+__device__ __noinline__ int best_neighbour_f64(const DevMesh& m, const float3 q, const float4 sp, const int4 rg)
+{
+    const double sx = sp.x, sy = sp.y, sz = sp.z;
+    const double wx = (double)q.x - sx, wy = (double)q.y - sy, wz = (double)q.z - sz;
+    double best = 0.0;
+    int nxt = -1;
+    for (int k = rg.x; k < rg.y; ++k) {
+        const float4 a = m.adj[k];
+        const double dx = (double)a.x - sx, dy = (double)a.y - sy, dz = (double)a.z - sz;
+        const double val = wx * dx + wy * dy + wz * dz - 0.5 * (dx * dx + dy * dy + dz * dz);
+        if (val > best) {
+            best = val;
+            nxt = __float_as_int(a.w);
+        }
+    }
+    return nxt;
+}
+
+// Cell Locate: greedy walk on the Delaunay graph from the seed site.  The
+// predicate is evaluated in FP32 with a bound on its rounding error; a step
+// is taken only on a certified improvement, and when no neighbour is
+// certified better but one lies within the bound the site's neighbours are
+// re-evaluated in FP64.  The walk therefore stops exactly where an FP64 walk
+// would (a local, hence global, minimum on the Delaunay graph).
 template <bool kCtr>
 __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned long long& steps,
                                       unsigned long long& adj_read)
 {
     int s = m.seed[seed_cell(m, q)];
-    const double qx = q.x, qy = q.y, qz = q.z;
     for (int it = 0; it < kWalkCap; ++it) {
-        const float4 sp = m.site_xyz[s];
-        const int4 rg = m.site_rng[s];
-        const double wx = qx - (double)sp.x, wy = qy - (double)sp.y, wz = qz - (double)sp.z;
-        double best = 0.0;
+        const float4 sp = m.site_rec[2 * s];
+        const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
+        const float wn = fabsf(wx) + fabsf(wy) + fabsf(wz);
+        float best = 0.f;
         int nxt = -1;
-        for (int k = rg.x; k < rg.y; ++k) {
-            const float4 a = m.adj[k];
-            const double dx = (double)a.x - (double)sp.x;
-            const double dy = (double)a.y - (double)sp.y;
-            const double dz = (double)a.z - (double)sp.z;
-            const double val = wx * dx + wy * dy + wz * dz - 0.5 * (dx * dx + dy * dy + dz * dz);
-            if (val > best) {
-                best = val;
-                nxt = __float_as_int(a.w);
+        bool unsure = false;
+        for (int k0 = rg.x; k0 < rg.y; k0 += 4) {
+            float4 a[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a[k] = m.adj[min(k0 + k, rg.y - 1)];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float dx = a[k].x - sp.x, dy = a[k].y - sp.y, dz = a[k].z - sp.z;
+                const float dn = fabsf(dx) + fabsf(dy) + fabsf(dz);
+                const float val = wx * dx + wy * dy + wz * dz - 0.5f * (dx * dx + dy * dy + dz * dz);
+                // |error| <= ~8 u (|w|_1 |d|_1 + |d|_1^2); 2^-19 leaves a 4x margin
+                const float tol = 1.9073486e-6f * dn * (wn + dn);
+                unsure |= fabsf(val) <= tol;
+                // repeated tail entries give the same value: never a strict improvement
+                if (val - tol > best) {
+                    best = val - tol;
+                    nxt = __float_as_int(a[k].w);
+                }
             }
         }
         if (kCtr) {
             steps += 1;
             adj_read += (unsigned long long)(rg.y - rg.x);
         }
+        if (nxt < 0 && unsure) nxt = best_neighbour_f64(m, q, sp, rg);
         if (nxt < 0) break;
         s = nxt;
     }
     return s;
 }
 
+// Best triangle so far: idx >= 0 is a list entry, idx <= -2 the triangle
+// slot -(idx + 2) (fallback search), -1 none.
 struct Best {
     float d2;
-    int slot;
+    int idx;
     float v, w;
 };
 
-// List Search over the located site's interception list.
+// List Search over the located site's interception list.  Entries are
+// fetched kChunk at a time (all loads issued before any is used) so that
+// the scan keeps several requests in flight despite its data-dependent exit.
+constexpr int kChunk = 4;
+
 template <bool kCtr>
 __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, const int s,
                                             unsigned long long& list_read, unsigned long long& exact,
                                             unsigned long long& list_len)
 {
-    const float4 sp = m.site_xyz[s];
-    const int4 rg = m.site_rng[s];
+    const float4 sp = m.site_rec[2 * s];
+    const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
     const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
     // |q - s| rounded up so that the early-exit bound stays conservative
     const float dqs = sqrtf(wx * wx + wy * wy + wz * wz) * 1.000001f;
     Best b{kInf, -1, 0.f, 0.f};
     float dmin = kInf;
-    int e = rg.z;
-    for (; e < rg.w; ++e) {
-        const int2 ax = m.list_aux[e];
-        if (__int_as_float(ax.y) - dqs >= dmin) break;
-        const float4 c = m.list_sph[e];
-        const float dx = q.x - c.x, dy = q.y - c.y, dz = q.z - c.z;
-        const float lim = dmin + c.w;
-        if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) continue;
-        const float4* r = m.tri_rec + 3 * (int64_t)ax.x;
-        float v, w;
-        const float d2 = closest_point(q, r[0], r[1], r[2], v, w);
-        if (kCtr) exact += 1;
-        if (d2 < b.d2) {
-            b.d2 = d2;
-            b.slot = ax.x;
-            b.v = v;
-            b.w = w;
-            dmin = sqrtf(d2);
+    int stop = rg.w;
+    for (int e = rg.z; e < stop; e += kChunk) {
+        // sphere (c, r) and (a, ell) of kChunk entries; the rest of an entry
+        // (e1, e2) shares their cache line
+        float4 c[kChunk], a[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const int idx = min(e + k, rg.w - 1);
+            c[k] = m.list_rec[4 * (int64_t)idx];
+            a[k] = m.list_rec[4 * (int64_t)idx + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            if (e + k >= stop) break;
+            // sorted by ell: no later entry can beat d_min (triangle inequality)
+            if (a[k].w - dqs >= dmin) {
+                stop = e + k;
+                break;
+            }
+            const float dx = q.x - c[k].x, dy = q.y - c[k].y, dz = q.z - c[k].z;
+            const float lim = dmin + c[k].w;
+            if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) continue;
+            const int64_t idx = e + k;
+            const float4 f2 = m.list_rec[4 * idx + 2], f3 = m.list_rec[4 * idx + 3];
+            float v, w;
+            const float d2 = closest_point(q, make_float3(a[k].x, a[k].y, a[k].z), make_float3(f2.x, f2.y, f2.z),
+                                           make_float3(f3.x, f3.y, f3.z), f2.w, v, w);
+            if (kCtr) exact += 1;
+            if (d2 < b.d2) {
+                b.d2 = d2;
+                b.idx = (int)idx;
+                b.v = v;
+                b.w = w;
+                dmin = sqrtf(d2);
+            }
         }
     }
     if (kCtr) {
-        list_read += (unsigned long long)(e - rg.z);
+        list_read += (unsigned long long)(stop - rg.z);
         list_len += (unsigned long long)(rg.w - rg.z);
     }
     return b;
@@ -205,8 +289,8 @@ __device__ Best bvh_search(const DevMesh& m, const float3 q)
             for (int slot = a; slot < a - c; ++slot) {
                 const float4* r = m.tri_rec + 3 * (int64_t)slot;
                 float v, w;
-                const float d2 = closest_point(q, r[0], r[1], r[2], v, w);
-                if (d2 < b.d2) { b.d2 = d2; b.slot = slot; b.v = v; b.w = w; }
+                const float d2 = closest_point_rec(q, r, v, w);
+                if (d2 < b.d2) { b.d2 = d2; b.idx = -slot - 2; b.v = v; b.w = w; }
             }
         } else if (sp + 2 <= 64) {
             stack[sp++] = c;       // right child
@@ -220,13 +304,14 @@ __device__ Best bvh_search(const DevMesh& m, const float3 q)
 // when fused, the gradient.  Shared by the plain and the batched kernels so
 // that both give bitwise identical results.
 template <bool kFused, bool kCtr>
-__device__ __forceinline__ void run_query(const DevMesh& m, const int64_t i, const float* __restrict__ qp,
-                                          float* __restrict__ dist, int32_t* __restrict__ tri,
-                                          float* __restrict__ closest, const float* __restrict__ gdist,
-                                          float* __restrict__ grad_q, float* __restrict__ grad_v,
-                                          unsigned long long* __restrict__ ctr)
+__device__ __forceinline__ void run_query(const DevMesh& m, const int64_t iq, const int64_t i,
+                                          const float* __restrict__ qp, float* __restrict__ dist,
+                                          int32_t* __restrict__ tri, float* __restrict__ closest,
+                                          const float* __restrict__ gdist, float* __restrict__ grad_q,
+                                          float* __restrict__ grad_v, unsigned long long* __restrict__ ctr)
 {
-    const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
+    // the point is read at iq (its slot in qp), every output and gradient at i
+    const float3 q = make_float3(qp[3 * iq], qp[3 * iq + 1], qp[3 * iq + 2]);
     unsigned long long steps = 0, adj_read = 0, list_read = 0, exact = 0, list_len = 0, fb = 0;
     Best b{kInf, -1, 0.f, 0.f};
     const bool finite = isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
@@ -235,7 +320,7 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const int64_t i, con
             const int s = locate<kCtr>(m, q, steps, adj_read);
             b = list_search<kCtr>(m, q, s, list_read, exact, list_len);
         }
-        if (b.slot < 0) {
+        if (b.idx == -1) {
             b = bvh_search(m, q);
             fb = 1;
         }
@@ -248,7 +333,7 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const int64_t i, con
         atomicAdd(&ctr[CTR_FALLBACK], fb);
         atomicAdd(&ctr[CTR_LIST_LEN], list_len);
     }
-    if (b.slot < 0) {
+    if (b.idx == -1) {
         const float nan = __int_as_float(0x7fc00000);
         dist[i] = nan;
         if (tri) tri[i] = -1;
@@ -264,11 +349,27 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const int64_t i, con
         }
         return;
     }
-    const float4* r = m.tri_rec + 3 * (int64_t)b.slot;
-    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+    // the winner's vertex a, edges e1, e2 and caller id: from its list entry
+    // (just scanned, so cache-resident), or from the triangle records
+    float4 r0, r1, r2;
+    int user;
+    if (b.idx >= 0) {
+        const float4* L = m.list_rec + 4 * (int64_t)b.idx;
+        r0 = L[1];
+        r1 = L[2];
+        r2 = L[3];
+        user = __float_as_int(r2.w);
+    } else {
+        const int slot = -b.idx - 2;
+        const float4* r = m.tri_rec + 3 * (int64_t)slot;
+        r0 = r[0];
+        r1 = r[1];
+        r2 = r[2];
+        user = m.tri_user[slot];
+    }
     const float d = sqrtf(b.d2);
     dist[i] = d;
-    if (tri) tri[i] = m.tri_user[b.slot];
+    if (tri) tri[i] = user;
     if (closest) {
         closest[3 * i] = r0.x + b.v * r1.x + b.w * r2.x;
         closest[3 * i + 1] = r0.y + b.v * r1.y + b.w * r2.y;
@@ -290,7 +391,7 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const int64_t i, con
             grad_q[3 * i + 2] = g * nz;
         }
         if (grad_v && d > 0.f && g != 0.f) {
-            const int4 vid = m.tri_vid[b.slot];
+            const int4 vid = m.tri_vid[user];
             const float lam[3] = {1.f - b.v - b.w, b.v, b.w};
             const int ids[3] = {vid.x, vid.y, vid.z};
 #pragma unroll
@@ -306,13 +407,25 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const int64_t i, con
     }
 }
 
+// Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
+// b mod x).  Remapping block b to logical block (b mod x) * per + b / x gives
+// every XCD one contiguous range of the sorted points, so each XCD's L2 sees
+// one spatially coherent region instead of all of them.
+__device__ __forceinline__ int64_t xcd_block(const int xcds, const int64_t per)
+{
+    const int64_t b = blockIdx.x;
+    return (b % xcds) * per + b / xcds;
+}
+
 template <bool kFused, bool kCtr>
 __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArgs a)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = gridDim.x / a.xcds;
+    const int64_t j = xcd_block(a.xcds, per) * blockDim.x + threadIdx.x;
     if (j >= a.n) return;
     const int64_t i = a.perm ? (int64_t)a.perm[j] : j;
-    run_query<kFused, kCtr>(m, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, a.grad_v, a.ctr);
+    run_query<kFused, kCtr>(m, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q,
+                            a.grad_v, a.ctr);
 }
 
 // Persistent batched kernel: each wavefront takes work items (up to `tile`
@@ -337,7 +450,7 @@ __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__
         const int64_t base = a.q_off[mi];
         for (int64_t j = first + lane; j < last; j += 64) {
             const int64_t i = base + (perm ? (int64_t)perm[j] : j);
-            run_query<kFused, false>(m, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, gv, nullptr);
+            run_query<kFused, false>(m, i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, gv, nullptr);
         }
     }
 }
@@ -356,7 +469,7 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
         const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
         const float4* r = m.tri_rec + 3 * (int64_t)slot;
         const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-        d = sqrtf(closest_point(q, r0, r1, r2, v, w));
+        d = sqrtf(closest_point_rec(q, r, v, w));
         g = gd[i];
         if (d > 0.f) {
             const float inv = 1.f / d;
@@ -371,7 +484,7 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
         grad_q[3 * i + 2] = g * nz;
     }
     if (grad_v && slot >= 0 && d > 0.f && g != 0.f) {
-        const int4 vid = m.tri_vid[slot];
+        const int4 vid = m.tri_vid[t];
         const float lam[3] = {1.f - v - w, v, w};
         const int ids[3] = {vid.x, vid.y, vid.z};
 #pragma unroll
@@ -396,18 +509,117 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n)
     if (i < n) p[i] = v;
 }
 
-__global__ void reorder_count_kernel(const DevMesh m, const float* __restrict__ qp, int64_t n,
-                                     uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
-                                     uint32_t* __restrict__ cnt)
+__device__ __forceinline__ uint32_t spread3(uint32_t x)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    x &= 0x3ff;
+    x = (x | (x << 16)) & 0x030000ff;
+    x = (x | (x << 8)) & 0x0300f00f;
+    x = (x | (x << 4)) & 0x030c30c3;
+    x = (x | (x << 2)) & 0x09249249;
+    return x;
+}
+
+// Morton code of a point's cell in the 2^bits-per-axis sort grid over the
+// seed-grid box; non-finite points and points outside the domain box get
+// the largest code.
+__device__ __forceinline__ uint32_t point_key(const DevMesh& m, const float* __restrict__ qp, int64_t i,
+                                              int bits, float sx, float sy, float sz)
+{
     const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
-    uint32_t k = (uint32_t)m.n_cells;
-    if (isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && in_domain(m, q))
-        k = (uint32_t)m.cell_rank[seed_cell(m, q)];
-    key[i] = k;
-    rank[i] = atomicAdd(&cnt[k], 1u);
+    if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && in_domain(m, q))) return (1u << (3 * bits)) - 1u;
+    const int g = (1 << bits) - 1;
+    const uint32_t ix = (uint32_t)min(max((int)floorf((q.x - m.gorg[0]) * sx), 0), g);
+    const uint32_t iy = (uint32_t)min(max((int)floorf((q.y - m.gorg[1]) * sy), 0), g);
+    const uint32_t iz = (uint32_t)min(max((int)floorf((q.z - m.gorg[2]) * sz), 0), g);
+    return spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2);
+}
+
+// LSD radix sort of (key, point index), 8 bits per pass.  A tile of
+// kSortTile consecutive elements per workgroup: the upsweep counts digits in
+// LDS; after a scan of the (digit, tile) counts the downsweep writes every
+// element to its digit's range, ranked stably within the tile by wavefront
+// ballots over the digit bits.  The first pass computes the keys from the
+// points themselves.
+constexpr int kSortBlock = 256;
+constexpr int kSortIters = 16;
+constexpr int kSortTile = kSortBlock * kSortIters;
+
+template <bool kFromPoints>
+__global__ void __launch_bounds__(kSortBlock) radix_upsweep(const DevMesh m, const float* __restrict__ qp,
+                                                            const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                            int bits, float sx, float sy, float sz,
+                                                            uint32_t* __restrict__ counts, int64_t n_tiles)
+{
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortIters; ++it) {
+        const int64_t idx = base + it * kSortBlock + threadIdx.x;
+        if (idx < n) {
+            const uint32_t key = kFromPoints ? point_key(m, qp, idx, bits, sx, sy, sz) : keys[idx];
+            atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+template <bool kFromPoints>
+__global__ void __launch_bounds__(kSortBlock) radix_downsweep(
+    const DevMesh m, const float* __restrict__ qp, const uint32_t* __restrict__ keys_in,
+    const int32_t* __restrict__ vals_in, int64_t n, int shift, int bits, float sx, float sy, float sz,
+    const uint32_t* __restrict__ offsets, int64_t n_tiles, uint32_t* __restrict__ keys_out,
+    int32_t* __restrict__ vals_out, float* __restrict__ sorted_q)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kSortBlock / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    run[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < kSortIters; ++it) {
+#pragma unroll
+        for (int w = 0; w < kSortBlock / 64; ++w) wcnt[w][tid] = 0u;
+        __syncthreads();
+        const int64_t idx = base + it * kSortBlock + tid;
+        const bool valid = idx < n;
+        uint32_t key = 0u;
+        int32_t val = 0;
+        if (valid) {
+            key = kFromPoints ? point_key(m, qp, idx, bits, sx, sy, sz) : keys_in[idx];
+            val = kFromPoints ? (int32_t)idx : vals_in[idx];
+        }
+        const uint32_t d = (key >> shift) & 255u;
+        // lanes of this wavefront holding the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m1 = __ballot(bit);
+            peers &= bit ? m1 : ~m1;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (valid && rank == 0u) wcnt[wid][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+            if (sorted_q) {
+                sorted_q[3 * (int64_t)pos] = qp[3 * (int64_t)val];
+                sorted_q[3 * (int64_t)pos + 1] = qp[3 * (int64_t)val + 1];
+                sorted_q[3 * (int64_t)pos + 2] = qp[3 * (int64_t)val + 2];
+            }
+        }
+        __syncthreads();
+        uint32_t add = 0u;
+#pragma unroll
+        for (int w = 0; w < kSortBlock / 64; ++w) add += wcnt[w][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
 }
 
 constexpr int kScanBlock = 1024;
@@ -462,14 +674,6 @@ __global__ void scan_add_kernel(uint32_t* __restrict__ data, int64_t n, const ui
     if (i < n) data[i] += sums[i / kScanTile];
 }
 
-__global__ void reorder_scatter_kernel(int64_t n, const uint32_t* __restrict__ key,
-                                       const uint32_t* __restrict__ rank, const uint32_t* __restrict__ off,
-                                       int32_t* __restrict__ perm)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) perm[off[key[i]] + rank[i]] = (int32_t)i;
-}
-
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // Exclusive scan of n uint32 in place; tmp holds scan_levels scratch.
@@ -501,13 +705,18 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
                           hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
-    const unsigned g = grid_for(a.n, block);
+    // pad the grid to a multiple of the XCD count (see xcd_block)
+    const int64_t nb = (a.n + block - 1) / block;
+    const int x = a.xcds > 0 ? a.xcds : 1;
+    const unsigned g = (unsigned)(((nb + x - 1) / x) * x);
+    FwdArgs args = a;
+    args.xcds = x;
     if (fused) {
-        if (counters) fwd_kernel<true, true><<<g, block, 0, st>>>(m, a);
-        else fwd_kernel<true, false><<<g, block, 0, st>>>(m, a);
+        if (counters) fwd_kernel<true, true><<<g, block, 0, st>>>(m, args);
+        else fwd_kernel<true, false><<<g, block, 0, st>>>(m, args);
     } else {
-        if (counters) fwd_kernel<false, true><<<g, block, 0, st>>>(m, a);
-        else fwd_kernel<false, false><<<g, block, 0, st>>>(m, a);
+        if (counters) fwd_kernel<false, true><<<g, block, 0, st>>>(m, args);
+        else fwd_kernel<false, false><<<g, block, 0, st>>>(m, args);
     }
     return hipGetLastError();
 }
@@ -520,27 +729,75 @@ hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const in
     return hipGetLastError();
 }
 
-size_t reorder_workspace_bytes(int64_t n, int32_t n_cells)
+// Sort-grid resolution: 2^bits cells per axis, the finest grid with at most
+// two cells per point (finer sorting keeps a wavefront's points on fewer
+// sites; measured best on the 10M-point workload).
+int sort_bits(int64_t n)
 {
-    const int64_t buckets = (int64_t)n_cells + 1;
-    return sizeof(uint32_t) * (size_t)(3 * n + buckets + scan_scratch(buckets) + 64);
+    int b = 2;
+    while (b < 8 && (int64_t)1 << (3 * (b + 1)) <= 2 * n) ++b;
+    return b;
 }
 
-hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, void* ws, const int32_t** perm_out,
-                          hipStream_t st)
+size_t reorder_workspace_bytes(int64_t n, int bits)
 {
-    const int64_t buckets = (int64_t)m.n_cells + 1;
-    uint32_t* key = (uint32_t*)ws;
-    uint32_t* rank = key + n;
-    int32_t* perm = (int32_t*)(rank + n);
-    uint32_t* cnt = (uint32_t*)(perm + n);
-    uint32_t* tmp = cnt + buckets;
-    fill_u32_kernel<<<grid_for(buckets, 256), 256, 0, st>>>(cnt, 0u, buckets);
-    reorder_count_kernel<<<grid_for(n, 256), 256, 0, st>>>(m, q, n, key, rank, cnt);
-    hipError_t e = exclusive_scan(cnt, buckets, tmp, st);
-    if (e != hipSuccess) return e;
-    reorder_scatter_kernel<<<grid_for(n, 256), 256, 0, st>>>(n, key, rank, cnt, perm);
-    *perm_out = perm;
+    (void)bits;
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t nc = 256 * n_tiles;
+    return sizeof(uint32_t) * (size_t)(4 * n + nc + scan_scratch(nc) + 64);
+}
+
+const int32_t* reorder_perm_location(void* ws, int64_t n, int bits)
+{
+    if (bits <= 0) bits = sort_bits(n);
+    const int passes = (3 * bits + 7) / 8;
+    // passes alternate between (ka, va) and (kb, vb); see launch_reorder
+    uint32_t* ka = (uint32_t*)ws;
+    return (passes % 2 == 1) ? (const int32_t*)(ka + n) : (const int32_t*)(ka + 3 * n);
+}
+
+hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, int bits, void* ws,
+                          const int32_t** perm_out, hipStream_t st, float* sorted_q)
+{
+    if (bits <= 0) bits = sort_bits(n);
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t nc = 256 * n_tiles;
+    uint32_t* ka = (uint32_t*)ws;
+    int32_t* va = (int32_t*)(ka + n);
+    uint32_t* kb = (uint32_t*)(va + n);
+    int32_t* vb = (int32_t*)(kb + n);
+    uint32_t* counts = (uint32_t*)(vb + n);
+    uint32_t* tmp = counts + nc;
+    // the sort grid spans the seed-grid box
+    const float G = (float)(1 << bits);
+    const float cell = 1.0f / m.ginv;
+    const float sx = G / (m.gdim[0] * cell), sy = G / (m.gdim[1] * cell), sz = G / (m.gdim[2] * cell);
+    const int key_bits = 3 * bits;
+    const unsigned grid = (unsigned)n_tiles;
+    uint32_t *kin = nullptr, *kout = ka;
+    int32_t *vin = nullptr, *vout = va;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        float* sq = (shift + 8 >= key_bits) ? sorted_q : nullptr;  // last pass
+        if (shift == 0) {
+            radix_upsweep<true><<<grid, kSortBlock, 0, st>>>(m, q, nullptr, n, shift, bits, sx, sy, sz, counts, n_tiles);
+        } else {
+            radix_upsweep<false><<<grid, kSortBlock, 0, st>>>(m, q, kin, n, shift, bits, sx, sy, sz, counts, n_tiles);
+        }
+        hipError_t e = exclusive_scan(counts, nc, tmp, st);
+        if (e != hipSuccess) return e;
+        if (shift == 0) {
+            radix_downsweep<true><<<grid, kSortBlock, 0, st>>>(m, q, nullptr, nullptr, n, shift, bits, sx, sy, sz,
+                                                               counts, n_tiles, kout, vout, sq);
+        } else {
+            radix_downsweep<false><<<grid, kSortBlock, 0, st>>>(m, q, kin, vin, n, shift, bits, sx, sy, sz, counts,
+                                                                n_tiles, kout, vout, sq);
+        }
+        kin = kout;
+        vin = vout;
+        kout = (kout == ka) ? kb : ka;
+        vout = (vout == va) ? vb : va;
+    }
+    *perm_out = vin;
     return hipGetLastError();
 }
 

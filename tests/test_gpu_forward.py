@@ -47,11 +47,37 @@ def test_c0_launch_configs_bitwise(dev, c0):
     ref = run(dev, m, c["Q"])
     for bs in (64, 512, 1024):
         for reorder in (0, 1):
-            m.set_query_config(block_size=bs, reorder=reorder)
-            out = run(dev, m, c["Q"])
-            for a, b in zip(ref, out):
-                assert np.array_equal(a, b, equal_nan=True), (bs, reorder)
-    m.set_query_config(block_size=256, reorder=1)
+            for xcd in (1, 3, 8):
+                m.set_query_config(block_size=bs, reorder=reorder, xcd_groups=xcd)
+                out = run(dev, m, c["Q"])
+                for a, b in zip(ref, out):
+                    assert np.array_equal(a, b, equal_nan=True), (bs, reorder, xcd)
+    m.set_query_config(block_size=256, reorder=1, xcd_groups=8)
+
+
+@pytest.mark.parametrize("n", [1, 4095, 4097, 300_001])
+def test_sort_points_is_a_permutation(dev, c0, n):
+    c, m = c0
+    rng = np.random.default_rng(50 + n)
+    Q = rng.uniform(-1.5, 1.5, (n, 3)).astype(np.float32)
+    Q[: n // 10] *= 30.0                      # some points outside the domain box
+    qt = torch.from_numpy(Q).cuda()
+    order_t, sq = dev.sort_points(m, qt, want_sorted=True)
+    order = to_np(order_t)
+    assert np.array_equal(np.sort(order), np.arange(n))
+    assert np.array_equal(to_np(sq), Q[order])
+    # the two halves give exactly p2m_query's results
+    ref = dev.query(m, qt)
+    for a, b in zip(ref, dev.query_sorted(m, sq, order_t)):
+        assert torch.equal(a, b)
+    for a, b in zip(ref, dev.query_ordered(m, qt, order_t)):
+        assert torch.equal(a, b)
+    # spatially coherent: consecutive points are much closer than random pairs
+    if n > 1000:
+        inside = np.all(np.abs(Q[order]) <= 1.5, axis=1)
+        qs = Q[order][inside].astype(np.float64)
+        step = np.linalg.norm(np.diff(qs, axis=0), axis=1)
+        assert np.median(step) < 0.1 * np.median(np.linalg.norm(qs - qs[::-1], axis=1))
 
 
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 4097, 100_003])
