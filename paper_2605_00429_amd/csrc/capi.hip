@@ -364,9 +364,20 @@ int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n, const
     if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
     if (n == 0) return P2M_OK;
     if (!d_points || !d_tri || !d_grad_dist) return fail(P2M_ERR_INVALID_ARG, "null points, triangles or gradient");
+    if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
     DeviceGuard dg(h->device);
-    hipError_t e = p2m::launch_backward(h->dm, d_points, n, d_tri, d_grad_dist, d_grad_points, d_grad_vertices,
-                                        h->cfg.block_size, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    // Visiting the points in spatial order lets a workgroup combine the
+    // vertex gradients of neighbouring points before the global atomics.
+    const int32_t* order = nullptr;
+    if (h->cfg.reorder && d_grad_vertices) {
+        int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st);
+        if (rc != P2M_OK) return rc;
+        hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->cfg.sort_bits, h->ws, &order, st);
+        if (e != hipSuccess) return hip_fail(e, "reorder launch");
+    }
+    hipError_t e = p2m::launch_backward(h->dm, d_points, n, order, d_tri, d_grad_dist, d_grad_points,
+                                        d_grad_vertices, h->cfg.block_size, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return P2M_OK;
 }

@@ -41,6 +41,7 @@ struct FwdArgs {
     float* grad_v;           // fused only, nullable
     unsigned long long* ctr; // counters only
     int32_t xcds;            // blocks are spread over this many XCD groups (see launch_forward)
+    int32_t acc_slots;       // fused: LDS hash slots for vertex gradients (set by launch_forward)
 };
 
 // Arguments of the persistent batched kernel.  Queries of mesh i occupy
@@ -67,8 +68,10 @@ hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int
                         hipStream_t st);
 hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fused, bool counters,
                           hipStream_t st);
-hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* tri,
-                           const float* g, float* grad_q, float* grad_v, int block, hipStream_t st);
+// order (nullable): visit point order[j] at thread j.
+hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* order,
+                           const int32_t* tri, const float* g, float* grad_q, float* grad_v, int block,
+                           hipStream_t st);
 // Radix sort of queries by the Morton code of their cell in a 2^k grid
 // over the seed-grid box (k from n when bits = 0).  ws must hold
 // reorder_workspace_bytes(n) bytes; writes the order to *perm_out.

@@ -300,15 +300,71 @@ __device__ Best bvh_search(const DevMesh& m, const float3 q)
     return b;
 }
 
+// Vertex-gradient accumulators.  DirectAcc adds straight to global memory
+// (float32 atomics).  LdsAcc first combines a workgroup's contributions in a
+// hash table in LDS (points are processed in spatial order, so neighbouring
+// points share vertices), then adds one global atomic per distinct vertex;
+// an insertion that does not find a slot within kProbe steps goes global.
+struct DirectAcc {
+    float* gv;
+    __device__ __forceinline__ void add(int vid, float x, float y, float z) const
+    {
+        float* dst = gv + 3 * (int64_t)vid;
+        unsafeAtomicAdd(dst, x);
+        unsafeAtomicAdd(dst + 1, y);
+        unsafeAtomicAdd(dst + 2, z);
+    }
+};
+
+struct LdsAcc {
+    float* gv;
+    int* keys;
+    float* val;   // 3 per slot
+    int slots;    // power of two
+    static constexpr int kProbe = 32;
+
+    __device__ __forceinline__ void init() const
+    {
+        for (int s = threadIdx.x; s < slots; s += blockDim.x) {
+            keys[s] = -1;
+            val[3 * s] = 0.f;
+            val[3 * s + 1] = 0.f;
+            val[3 * s + 2] = 0.f;
+        }
+    }
+    __device__ __forceinline__ void add(int vid, float x, float y, float z) const
+    {
+        uint32_t h = (uint32_t)vid * 2654435761u;
+        for (int p = 0; p < kProbe; ++p) {
+            const int slot = (int)((h + (uint32_t)p) & (uint32_t)(slots - 1));
+            const int prev = atomicCAS(&keys[slot], -1, vid);
+            if (prev == -1 || prev == vid) {
+                atomicAdd(&val[3 * slot], x);
+                atomicAdd(&val[3 * slot + 1], y);
+                atomicAdd(&val[3 * slot + 2], z);
+                return;
+            }
+        }
+        DirectAcc{gv}.add(vid, x, y, z);
+    }
+    __device__ __forceinline__ void flush() const
+    {
+        for (int s = threadIdx.x; s < slots; s += blockDim.x) {
+            const int k = keys[s];
+            if (k >= 0) DirectAcc{gv}.add(k, val[3 * s], val[3 * s + 1], val[3 * s + 2]);
+        }
+    }
+};
+
 // One query end to end: locate, list search (or fallback), outputs and,
 // when fused, the gradient.  Shared by the plain and the batched kernels so
 // that both give bitwise identical results.
-template <bool kFused, bool kCtr>
+template <bool kFused, bool kCtr, class Acc>
 __device__ __forceinline__ void run_query(const DevMesh& m, const int64_t iq, const int64_t i,
                                           const float* __restrict__ qp, float* __restrict__ dist,
                                           int32_t* __restrict__ tri, float* __restrict__ closest,
                                           const float* __restrict__ gdist, float* __restrict__ grad_q,
-                                          float* __restrict__ grad_v, unsigned long long* __restrict__ ctr)
+                                          const Acc& acc, unsigned long long* __restrict__ ctr)
 {
     // the point is read at iq (its slot in qp), every output and gradient at i
     const float3 q = make_float3(qp[3 * iq], qp[3 * iq + 1], qp[3 * iq + 2]);
@@ -390,7 +446,7 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const int64_t iq, co
             grad_q[3 * i + 1] = g * ny;
             grad_q[3 * i + 2] = g * nz;
         }
-        if (grad_v && d > 0.f && g != 0.f) {
+        if (acc.gv && d > 0.f && g != 0.f) {
             const int4 vid = m.tri_vid[user];
             const float lam[3] = {1.f - b.v - b.w, b.v, b.w};
             const int ids[3] = {vid.x, vid.y, vid.z};
@@ -398,10 +454,7 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const int64_t iq, co
             for (int k = 0; k < 3; ++k) {
                 const float s = -g * lam[k];
                 if (s == 0.f) continue;
-                float* dst = grad_v + 3 * (int64_t)ids[k];
-                unsafeAtomicAdd(dst, s * nx);
-                unsafeAtomicAdd(dst + 1, s * ny);
-                unsafeAtomicAdd(dst + 2, s * nz);
+                acc.add(ids[k], s * nx, s * ny, s * nz);
             }
         }
     }
@@ -422,10 +475,26 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
 {
     const int64_t per = gridDim.x / a.xcds;
     const int64_t j = xcd_block(a.xcds, per) * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
-    const int64_t i = a.perm ? (int64_t)a.perm[j] : j;
-    run_query<kFused, kCtr>(m, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q,
-                            a.grad_v, a.ctr);
+    if (!kFused) {
+        if (j >= a.n) return;
+        const int64_t i = a.perm ? (int64_t)a.perm[j] : j;
+        run_query<false, kCtr>(m, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, nullptr, nullptr,
+                               DirectAcc{nullptr}, a.ctr);
+        return;
+    }
+    // fused: vertex gradients combined per workgroup in LDS (every thread
+    // reaches both barriers)
+    extern __shared__ int acc_smem[];
+    const LdsAcc acc{a.grad_v, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
+    if (a.grad_v) acc.init();
+    __syncthreads();
+    if (j < a.n) {
+        const int64_t i = a.perm ? (int64_t)a.perm[j] : j;
+        run_query<true, kCtr>(m, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q,
+                              acc, a.ctr);
+    }
+    __syncthreads();
+    if (a.grad_v) acc.flush();
 }
 
 // Persistent batched kernel: each wavefront takes work items (up to `tile`
@@ -446,57 +515,63 @@ __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__
         const int64_t last = min(first + (int64_t)a.tile, count);
         const DevMesh m = meshes[mi];
         const int32_t* perm = a.perm[mi];
-        float* gv = kFused ? a.grad_v[mi] : nullptr;
+        const DirectAcc acc{kFused ? a.grad_v[mi] : nullptr};
         const int64_t base = a.q_off[mi];
         for (int64_t j = first + lane; j < last; j += 64) {
             const int64_t i = base + (perm ? (int64_t)perm[j] : j);
-            run_query<kFused, false>(m, i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, gv, nullptr);
+            run_query<kFused, false>(m, i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, acc, nullptr);
         }
     }
 }
 
 __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float* __restrict__ qp, int64_t n,
+                                                   const int32_t* __restrict__ order,
                                                    const int32_t* __restrict__ tri, const float* __restrict__ gd,
-                                                   float* __restrict__ grad_q, float* __restrict__ grad_v)
+                                                   float* __restrict__ grad_q, float* __restrict__ grad_v,
+                                                   int acc_slots)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int t = tri[i];
-    float nx = 0.f, ny = 0.f, nz = 0.f, g = 0.f, v = 0.f, w = 0.f, d = 0.f;
-    int slot = -1;
-    if (t >= 0 && t < m.n_tris) {
-        slot = m.tri_slot[t];
-        const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
-        const float4* r = m.tri_rec + 3 * (int64_t)slot;
-        const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-        d = sqrtf(closest_point_rec(q, r, v, w));
-        g = gd[i];
-        if (d > 0.f) {
-            const float inv = 1.f / d;
-            nx = (q.x - r0.x - v * r1.x - w * r2.x) * inv;
-            ny = (q.y - r0.y - v * r1.y - w * r2.y) * inv;
-            nz = (q.z - r0.z - v * r1.z - w * r2.z) * inv;
+    extern __shared__ int acc_smem[];
+    const LdsAcc acc{grad_v, acc_smem, (float*)(acc_smem + acc_slots), acc_slots};
+    if (grad_v) acc.init();
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) {
+        const int64_t i = order ? (int64_t)order[j] : j;
+        const int t = tri[i];
+        float nx = 0.f, ny = 0.f, nz = 0.f, g = 0.f, v = 0.f, w = 0.f, d = 0.f;
+        if (t >= 0 && t < m.n_tris) {
+            const int slot = m.tri_slot[t];
+            const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
+            const float4* r = m.tri_rec + 3 * (int64_t)slot;
+            const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+            d = sqrtf(closest_point_rec(q, r, v, w));
+            g = gd[i];
+            if (d > 0.f) {
+                const float inv = 1.f / d;
+                nx = (q.x - r0.x - v * r1.x - w * r2.x) * inv;
+                ny = (q.y - r0.y - v * r1.y - w * r2.y) * inv;
+                nz = (q.z - r0.z - v * r1.z - w * r2.z) * inv;
+            }
         }
-    }
-    if (grad_q) {
-        grad_q[3 * i] = g * nx;
-        grad_q[3 * i + 1] = g * ny;
-        grad_q[3 * i + 2] = g * nz;
-    }
-    if (grad_v && slot >= 0 && d > 0.f && g != 0.f) {
-        const int4 vid = m.tri_vid[t];
-        const float lam[3] = {1.f - v - w, v, w};
-        const int ids[3] = {vid.x, vid.y, vid.z};
+        if (grad_q) {
+            grad_q[3 * i] = g * nx;
+            grad_q[3 * i + 1] = g * ny;
+            grad_q[3 * i + 2] = g * nz;
+        }
+        if (grad_v && d > 0.f && g != 0.f) {
+            const int4 vid = m.tri_vid[t];
+            const float lam[3] = {1.f - v - w, v, w};
+            const int ids[3] = {vid.x, vid.y, vid.z};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float s = -g * lam[k];
-            if (s == 0.f) continue;
-            float* dst = grad_v + 3 * (int64_t)ids[k];
-            unsafeAtomicAdd(dst, s * nx);
-            unsafeAtomicAdd(dst + 1, s * ny);
-            unsafeAtomicAdd(dst + 2, s * nz);
+            for (int k = 0; k < 3; ++k) {
+                const float s = -g * lam[k];
+                if (s == 0.f) continue;
+                acc.add(ids[k], s * nx, s * ny, s * nz);
+            }
         }
     }
+    __syncthreads();
+    if (grad_v) acc.flush();
 }
 
 // ---------------------------------------------------------------- reorder
@@ -676,6 +751,17 @@ __global__ void scan_add_kernel(uint32_t* __restrict__ data, int64_t n, const ui
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// LDS hash table for a workgroup's vertex gradients: a power of two at
+// least 4x the workgroup's 3 contributions per thread.
+inline int acc_slots_for(int block)
+{
+    int s = 1;
+    while (s < 4 * block) s <<= 1;
+    return s;
+}
+
+inline size_t acc_lds_bytes(int slots) { return (size_t)slots * 16; }
+
 // Exclusive scan of n uint32 in place; tmp holds scan_levels scratch.
 hipError_t exclusive_scan(uint32_t* data, int64_t n, uint32_t* tmp, hipStream_t st)
 {
@@ -712,8 +798,10 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
     FwdArgs args = a;
     args.xcds = x;
     if (fused) {
-        if (counters) fwd_kernel<true, true><<<g, block, 0, st>>>(m, args);
-        else fwd_kernel<true, false><<<g, block, 0, st>>>(m, args);
+        args.acc_slots = acc_slots_for(block);
+        const size_t lds = acc_lds_bytes(args.acc_slots);
+        if (counters) fwd_kernel<true, true><<<g, block, lds, st>>>(m, args);
+        else fwd_kernel<true, false><<<g, block, lds, st>>>(m, args);
     } else {
         if (counters) fwd_kernel<false, true><<<g, block, 0, st>>>(m, args);
         else fwd_kernel<false, false><<<g, block, 0, st>>>(m, args);
@@ -721,11 +809,14 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* tri,
-                           const float* g, float* grad_q, float* grad_v, int block, hipStream_t st)
+hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* order,
+                           const int32_t* tri, const float* g, float* grad_q, float* grad_v, int block,
+                           hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    bwd_kernel<<<grid_for(n, block), block, 0, st>>>(m, q, n, tri, g, grad_q, grad_v);
+    const int slots = acc_slots_for(block);
+    bwd_kernel<<<grid_for(n, block), block, acc_lds_bytes(slots), st>>>(m, q, n, order, tri, g, grad_q, grad_v,
+                                                                         slots);
     return hipGetLastError();
 }
 
