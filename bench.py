@@ -54,14 +54,31 @@ def load_traffic(kernel_hash, n_points):
 
 
 def bytes_per_query(ctr, n):
-    """Algorithmic bytes one query touches (each touch counted once):
-    point 12, order 4, seed cell 4, per visited site 32 (position + ranges),
-    adjacency entries 16 each, located site again 32, list entries 32 each
-    (bounding sphere, first vertex and ell), 32 more per exact test (the two
-    edge vectors and slot), the winner's record 48 + user id 4, outputs 20."""
-    per = (12 + 4 + 4 + 32 * ctr["walk_steps"] / n + 16 * ctr["adj_read"] / n + 32
-           + 32 * ctr["list_read"] / n + 32 * ctr["exact_tests"] / n + 52 + 20)
-    return per
+    """Algorithmic bytes of one forward query: what the method touches, each
+    item at its plain size (point 12, outputs 20, seed cell 4; per walk step
+    the site's position and adjacency range 8 and 16 per neighbour read; the
+    located site's list range 8; 16 per list entry scanned (bounding sphere);
+    per exact test the triangle id 4 and its record 48).  S, deg, L and E are
+    the instrumented counts of this run, not estimates."""
+    return (12 + 20 + 4 + 8 * ctr["walk_steps"] / n + 16 * ctr["adj_read"] / n + 8
+            + 16 * ctr["list_read"] / n + 52 * ctr["exact_tests"] / n)
+
+
+def layout_bytes_per_query(ctr, n):
+    """Bytes the kernel's own layout reads per query (each touch counted
+    once): point 12, order 4, seed 4, per visited site 32, adjacency entries
+    16, located site 32, 32 per scanned list entry (sphere, first vertex and
+    ell), 32 more per exact test, the winner's record 48 + id 4, outputs 20."""
+    return (12 + 4 + 4 + 32 * ctr["walk_steps"] / n + 16 * ctr["adj_read"] / n + 32
+            + 32 * ctr["list_read"] / n + 32 * ctr["exact_tests"] / n + 52 + 20)
+
+
+# Backward per query: q 12, tri 4, closest 12, dist 4, g 4, vertex ids 12,
+# triangle record 48, dL/dq 12, three vertex read-modify-writes 72.
+BWD_BYTES = 12 + 4 + 12 + 4 + 4 + 12 + 48 + 12 + 72
+# Fused forward+backward adds g 4, dL/dq 12, vertex ids 12 and the vertex
+# read-modify-writes 72 to the forward.
+FUSED_EXTRA = 4 + 12 + 12 + 72
 
 
 def main():
@@ -72,7 +89,7 @@ def main():
     ap.add_argument("--points", type=int, default=10_000_000, help="total points (half uniform, half near-surface)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward timings")
-    ap.add_argument("--cpu-sample", type=int, default=4000)
+    ap.add_argument("--cpu-sample", type=int, default=16000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy, the reference kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
@@ -123,6 +140,7 @@ def main():
     _, _, _, ctr = p2m.query_counters(mesh, q)
     torch.cuda.synchronize()
     bpq = bytes_per_query(ctr, n)
+    lbpq = layout_bytes_per_query(ctr, n)
     log(f"per query: walk steps {ctr['walk_steps'] / n:.2f}, adjacency read {ctr['adj_read'] / n:.1f}, "
         f"list read {ctr['list_read'] / n:.1f} of {ctr['list_len'] / n:.1f}, exact tests "
         f"{ctr['exact_tests'] / n:.2f}, fallback {ctr['fallback']}; {bpq:.0f} B/query")
@@ -179,7 +197,7 @@ def main():
         "config": {
             "workload": "displaced icosphere-7 (327,680 triangles, 163,842 vertices); "
                         f"{n} points: {n_half} uniform in box x1.2 + {n - n_half} near-surface sigma 0.5% diag",
-            "n_points": n, "n_triangles": len(F), "locate_predicate": "f64",
+            "n_points": n, "n_triangles": len(F),
         },
     }
 
@@ -191,8 +209,14 @@ def main():
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "kernel": "fwd_kernel (search: locate + list scan)", "kernel_ms": round(search_avg, 4),
-        "bytes_per_query": round(bpq, 1), "kernel_hash": kh,
+        "bytes_per_query": round(bpq, 1), "layout_bytes_per_query": round(lbpq, 1),
+        "layout_GBps": round(lbpq * n / (search_avg * 1e-3) / 1e9, 1), "kernel_hash": kh,
     }
+    if traffic:
+        result["roofline"]["traffic_GBps"] = round(traffic / (search_avg * 1e-3) / 1e9, 1)
+    # whole forward step (sort + search) against the same per-query bytes
+    result["forward_step_GBps"] = round(alg_bytes / (ms_per_step * 1e-3) / 1e9, 1)
+    result["forward_step_frac"] = round(result["forward_step_GBps"] / HBM_PEAK_GBS, 4)
     result["sort_ms"] = round(sum(sort_ms) / args.steps, 4)
     result["per_query"] = {k: round(v / n, 3) for k, v in ctr.items()}
     result["structure"] = {k: st[k] for k in ("n_sites", "n_aux_sites", "list_avg", "list_max", "adj_avg",
@@ -229,6 +253,10 @@ def main():
             ms = e0.elapsed_time(e1) / args.steps
             result[f"{name}_mqps"] = round(n / (ms * 1e-3) / 1e6, 2)
             result[f"{name}_ms"] = round(ms, 4)
+            per = bpq + (BWD_BYTES if name == "fwd_bwd" else FUSED_EXTRA)
+            result[f"{name}_GBps"] = round(per * n / (ms * 1e-3) / 1e9, 1)
+            result[f"{name}_frac"] = round(result[f"{name}_GBps"] / HBM_PEAK_GBS, 4)
+            result[f"{name}_vs_forward"] = round(result[f"{name}_mqps"] / mqps, 4)
             log(f"{name}: {ms:.3f} ms/step = {result[f'{name}_mqps']:.1f} Mq/s")
 
     if not args.no_cpu_baseline:
