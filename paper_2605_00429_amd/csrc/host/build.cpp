@@ -107,7 +107,7 @@ bool d3_less(const d3& a, const d3& b)
 struct CellWork {
     ClipCell cell;
     std::vector<std::pair<double, int32_t>> knn;
-    std::vector<int32_t> tested;
+    std::vector<int32_t> tested, found;
     std::vector<d3> corners, verified;
     std::vector<int32_t> faces;
     std::vector<Ball> balls;
@@ -150,9 +150,13 @@ void voronoi_cell(int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo,
         // and adds new ones (bitwise copies survive), so only new corners
         // need the exact check.
         w.verified.clear();
+        // Each pass finds, for every corner not yet verified, the nearest
+        // site closer to it than s (if any), then clips by all of them at
+        // once: cells with thousands of neighbours (near a rotational axis)
+        // need a few passes instead of one pass per neighbour.
         for (size_t guard = 0; guard <= P.size(); ++guard) {
             w.cell.corners(w.corners);
-            int32_t found = -1;
+            w.found.clear();
             for (const d3& x : w.corners) {
                 const double r2 = norm2(x);
                 if (4.0 * r2 <= dK2) continue;
@@ -161,14 +165,19 @@ void voronoi_cell(int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo,
                 // in squared distance) is skipped: the cell then stays a
                 // superset of the exact one, and the walk's stop region and
                 // the lists are both built from this computed cell.
-                found = kd.nearest_below(ps + x, r2 * (1.0 - kCornerSlack), w.tested, nullptr, true);
-                if (found >= 0) break;
-                w.verified.insert(std::upper_bound(w.verified.begin(), w.verified.end(), x, d3_less), x);
+                const int32_t f = kd.nearest_below(ps + x, r2 * (1.0 - kCornerSlack), w.tested);
+                if (f >= 0) w.found.push_back(f);
+                else w.verified.push_back(x);
             }
-            if (found < 0) break;
-            const d3 n = P[found] - ps;
-            w.cell.clip(n, 0.5 * norm2(n), found);
-            w.tested.insert(std::upper_bound(w.tested.begin(), w.tested.end(), found), found);
+            std::sort(w.verified.begin(), w.verified.end(), d3_less);
+            if (w.found.empty()) break;
+            std::sort(w.found.begin(), w.found.end());
+            w.found.erase(std::unique(w.found.begin(), w.found.end()), w.found.end());
+            for (int32_t f : w.found) {
+                const d3 n = P[f] - ps;
+                w.cell.clip(n, 0.5 * norm2(n), f);
+                w.tested.insert(std::upper_bound(w.tested.begin(), w.tested.end(), f), f);
+            }
         }
     }
     w.cell.corners(w.corners);

@@ -35,12 +35,17 @@ public:
 private:
     struct Face {
         int32_t id;
-        int32_t begin, count;
+        int32_t begin, count;  // vertex range in v_
+        d3 c;                  // bounding sphere of the face's vertices
+        double r;
     };
-    std::vector<Face> faces_, nfaces_;
-    std::vector<d3> v_, nv_;
+    void seal(Face& f) const;  // sets the bounding sphere
+    void compact();
+    std::vector<Face> faces_;
+    std::vector<d3> v_, tmp_;  // v_ also holds dead ranges until compact()
     std::vector<double> sd_;
     std::vector<d3> cut_;
+    size_t live_ = 0;          // vertices referenced by faces_
     double scale_ = 1.0;  // typical coordinate magnitude, for tolerances
 };
 

@@ -141,8 +141,8 @@ def test_small_and_degenerate_meshes(dev):
 
 @pytest.fixture(scope="module")
 def c1(dev):
-    # C1's recipe at 128 x 32 segments (16,640 triangles): the full 512 x 128
-    # mesh takes minutes of host preprocessing on its axis clusters
+    # C1's recipe at 128 x 32 segments (16,640 triangles), every output
+    # checked against the oracle
     c = gen.config_c1(20_000, 20_000, n_seg=128, n_ring=32)
     return c, dev.Mesh(c["V"], c["F"])
 
@@ -153,16 +153,10 @@ def test_c1_subset(dev, c1):
     print("C1 max|dd|/D, p99.9:", check_forward(c["V"], c["F"], c["Q"], d, t, cl, c["D"], label="C1"))
 
 
-@pytest.fixture(scope="module")
-def c2(dev):
-    c = gen.config_c2()     # full size: 10M points
-    return c, dev.Mesh(c["V"], c["F"])
-
-
-def test_c2_full_size_sampled(dev, c2):
-    """Full C2 workload in the benchmark's launch configuration; the oracle
-    checks a seeded sample of outputs one by one, invariants check all."""
-    c, m = c2
+def check_full_size(dev, c, m, n_sample, seed):
+    """The whole workload through p2m_query (the benchmark's launch
+    configuration); the oracle checks a seeded sample of outputs one by one,
+    invariants check all of them."""
     q = torch.from_numpy(c["Q"]).cuda()
     d, t, cl = dev.query(m, q)
     d2, t2, cl2 = dev.query(m, q)
@@ -170,14 +164,34 @@ def test_c2_full_size_sampled(dev, c2):
     assert torch.equal(d, d2) and torch.equal(t, t2) and torch.equal(cl, cl2)   # deterministic
     d, t, cl = to_np(d), to_np(t), to_np(cl)
     n = len(c["Q"])
-    rng = np.random.default_rng(2024)
-    idx = np.concatenate([rng.choice(n // 2, 1500, replace=False), n // 2 + rng.choice(n // 2, 1500, replace=False)])
-    print("C2 sample max|dd|/D, p99.9:", check_forward(c["V"], c["F"], c["Q"][idx], d[idx], t[idx], cl[idx],
-                                                       c["D"], label="C2"))
+    rng = np.random.default_rng(seed)
+    h = n_sample // 2
+    idx = np.concatenate([rng.choice(n // 2, h, replace=False), n // 2 + rng.choice(n - n // 2, h, replace=False)])
+    res = check_forward(c["V"], c["F"], c["Q"][idx], d[idx], t[idx], cl[idx], c["D"], label=c["name"])
     tol = 1e-5 * c["D"]
-    # invariants on every output: closest point on its triangle, |q - p| = d
     assert t.min() >= 0 and t.max() < len(c["F"])
     on = oracle.distance_to_triangles64(c["V"], c["F"], cl.astype(np.float64), t)
-    assert on.max() <= tol
+    assert on.max() <= tol                                  # closest point on its triangle
     dq = np.linalg.norm(c["Q"].astype(np.float64) - cl, axis=1)
-    assert np.abs(dq - d).max() <= tol
+    assert np.abs(dq - d).max() <= tol                      # |q - p| = d
+    return res
+
+
+def test_c1_full_size_sampled(dev):
+    """C1 at its full size: 512 x 128 cylinder + cone (263,168 triangles),
+    1M uniform + 1M near-surface points."""
+    c = gen.config_c1()
+    m = dev.Mesh(c["V"], c["F"])
+    print("C1 full sample max|dd|/D, p99.9:", check_full_size(dev, c, m, 3000, 2025))
+
+
+@pytest.fixture(scope="module")
+def c2(dev):
+    c = gen.config_c2()     # full size: 10M points
+    return c, dev.Mesh(c["V"], c["F"])
+
+
+def test_c2_full_size_sampled(dev, c2):
+    """Full C2 workload (10M points) in the benchmark's launch configuration."""
+    c, m = c2
+    print("C2 sample max|dd|/D, p99.9:", check_full_size(dev, c, m, 3000, 2024))
