@@ -81,6 +81,120 @@ BWD_BYTES = 12 + 4 + 12 + 4 + 4 + 12 + 48 + 12 + 72
 FUSED_EXTRA = 4 + 12 + 12 + 72
 
 
+def timed(fn, steps, warmup, stream):
+    """Average ms of fn() over `steps` calls after `warmup`, HIP events on
+    `stream`."""
+    import torch
+    for _ in range(max(1, warmup)):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_batched(args, plain_c2_mqps, stream):
+    """The batched multi-mesh form: 64 meshes of uneven sizes and kinds with
+    uneven query counts, forward and fused forward+backward as one
+    graph-captured persistent launch each, against the same work as one plain
+    call per mesh on the same stream."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2605_00429_amd as p2m
+
+    plan = gen.c4_plan()[: args.batched_meshes]
+    log(f"batched workload: generating {len(plan)} meshes and their points")
+    cfg = gen.config_c4(plan)
+    t0 = time.time()
+    meshes = [p2m.Mesh(c["V"], c["F"]) for c in cfg]
+    build_s = time.time() - t0
+    counts = [len(c["Q"]) for c in cfg]
+    n = int(sum(counts))
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    n_tris = int(sum(len(c["F"]) for c in cfg))
+    n_verts = [len(c["V"]) for c in cfg]
+    log(f"batched workload: {len(cfg)} meshes, {n_tris} triangles, {n} points; build {build_s:.1f}s")
+    dev = torch.device("cuda", 0)
+    q = torch.from_numpy(np.concatenate([c["Q"] for c in cfg], 0)).to(dev)
+    del cfg
+    g = torch.from_numpy(np.random.default_rng(2605_00429 + 4).normal(size=n).astype(np.float32)).to(dev)
+    dist = torch.empty(n, device=dev)
+    tri = torch.empty(n, dtype=torch.int32, device=dev)
+    cl = torch.empty((n, 3), device=dev)
+    gq = torch.empty((n, 3), device=dev)
+    voff = np.concatenate([[0], np.cumsum(n_verts)]).astype(np.int64)
+    gv_flat = torch.zeros((int(voff[-1]), 3), device=dev)
+    gvs = [gv_flat[voff[i]:voff[i + 1]] for i in range(len(meshes))]
+    qs = [q[off[i]:off[i + 1]] for i in range(len(meshes))]
+
+    # algorithmic bytes: per-mesh instrumented forwards (untimed)
+    alg = 0.0
+    for i, m in enumerate(meshes):
+        _, _, _, ctr = p2m.query_counters(m, qs[i])
+        alg += bytes_per_query(ctr, counts[i]) * counts[i] if counts[i] else 0.0
+    torch.cuda.synchronize()
+
+    b_fwd = p2m.Batch(meshes, counts, autotune=True)
+    b_fwd.bind(q, dist, tri, cl, stream=stream)
+    b_fus = p2m.Batch(meshes, counts, autotune=True)
+    b_fus.bind(q, dist, tri, cl, grad_dist=g, grad_points=gq, grad_vertices=gvs, stream=stream)
+
+    outs = [(dist[off[i]:off[i + 1]], tri[off[i]:off[i + 1]], cl[off[i]:off[i + 1]]) for i in range(len(meshes))]
+
+    def plain_fwd():
+        for i, m in enumerate(meshes):
+            p2m.lib().p2m_query(m.handle, p2m._ptr(qs[i]), counts[i], p2m._ptr(outs[i][0]), p2m._ptr(outs[i][1]),
+                                p2m._ptr(outs[i][2]), p2m._stream(stream))
+
+    def plain_fused():
+        gv_flat.zero_()
+        for i, m in enumerate(meshes):
+            p2m.lib().p2m_query_fused(m.handle, p2m._ptr(qs[i]), counts[i], p2m._ptr(g[off[i]:off[i + 1]]),
+                                      p2m._ptr(outs[i][0]), p2m._ptr(outs[i][1]), p2m._ptr(outs[i][2]),
+                                      p2m._ptr(gq[off[i]:off[i + 1]]), p2m._ptr(gvs[i]), p2m._stream(stream))
+
+    def batched_fused():
+        gv_flat.zero_()
+        b_fus.launch(stream=stream)
+
+    steps, warm = max(3, args.steps // 2), max(1, args.warmup)
+    ms_b = timed(lambda: b_fwd.launch(stream=stream), steps, warm, stream)
+    ms_p = timed(plain_fwd, steps, warm, stream)
+    ms_bf = timed(batched_fused, steps, warm, stream)
+    ms_pf = timed(plain_fused, steps, warm, stream)
+    mq = lambda ms: round(n / (ms * 1e-3) / 1e6, 2)
+    gbs = lambda per, ms: round(per / (ms * 1e-3) / 1e9, 1)
+    res = {
+        "workload": f"{len(meshes)} meshes (uv sphere, capped cylinder, capped cone, torus, displaced icosphere), "
+                    f"{n_tris} triangles, log-uniform 1e3-5e5 per mesh; {n} points, log-uniform 1e4-2e6 per "
+                    "mesh, half uniform in box x1.2, half near-surface sigma 0.5% diag",
+        "n_points": n, "n_triangles": n_tris, "build_s": round(build_s, 1),
+        "fwd_ms": round(ms_b, 4), "fwd_mqps": mq(ms_b),
+        "plain_fwd_ms": round(ms_p, 4), "plain_fwd_mqps": mq(ms_p),
+        "fwd_vs_plain": round(ms_p / ms_b, 4),
+        "fwd_vs_c2_plain_forward": round(mq(ms_b) / plain_c2_mqps, 4),
+        "fwd_bwd_ms": round(ms_bf, 4), "fwd_bwd_mqps": mq(ms_bf),
+        "plain_fwd_bwd_ms": round(ms_pf, 4), "plain_fwd_bwd_mqps": mq(ms_pf),
+        "fwd_bwd_vs_plain": round(ms_pf / ms_bf, 4),
+        "bytes_per_query": round(alg / n, 1),
+        "fwd_GBps": gbs(alg, ms_b), "fwd_frac": round(gbs(alg, ms_b) / HBM_PEAK_GBS, 4),
+        "fwd_bwd_GBps": gbs(alg + FUSED_EXTRA * n, ms_bf),
+        "fwd_bwd_frac": round(gbs(alg + FUSED_EXTRA * n, ms_bf) / HBM_PEAK_GBS, 4),
+        "launch_config": b_fwd.config(),
+    }
+    log(f"batched forward {ms_b:.3f} ms ({res['fwd_mqps']:.1f} Mq/s) vs {len(meshes)} plain calls "
+        f"{ms_p:.3f} ms; fused batched {ms_bf:.3f} ms vs plain {ms_pf:.3f} ms")
+    b_fwd.close()
+    b_fus.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +204,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward timings")
     ap.add_argument("--cpu-sample", type=int, default=16000)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-mesh measurement")
+    ap.add_argument("--batched-meshes", type=int, default=64, help="meshes of the batched workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy, the reference kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
@@ -258,6 +374,9 @@ def main():
             result[f"{name}_frac"] = round(result[f"{name}_GBps"] / HBM_PEAK_GBS, 4)
             result[f"{name}_vs_forward"] = round(result[f"{name}_mqps"] / mqps, 4)
             log(f"{name}: {ms:.3f} ms/step = {result[f'{name}_mqps']:.1f} Mq/s")
+
+    if not args.no_batched:
+        result["batched"] = bench_batched(args, mqps, stream)
 
     if not args.no_cpu_baseline:
         import oracle

@@ -178,6 +178,11 @@ int32_t p2m_build(const p2m_mesh_desc* mesh, const p2m_build_opts* opts, p2m_han
             h->upload_all();
         }
         h->H.stats.device_bytes = h->device_bytes;
+        // The host keeps only the triangle id of each list entry (for the
+        // inspection calls); the full 64 B records live on the device.
+        h->H.list_tri.resize(h->H.list_rec.size());
+        for (size_t k = 0; k < h->H.list_rec.size(); ++k) h->H.list_tri[k] = h->H.list_rec[k].tri;
+        std::vector<p2m::ListRec>().swap(h->H.list_rec);
     } catch (const p2m::Error& e) {
         delete h;
         return fail(e.code, e.what());
@@ -408,7 +413,7 @@ int32_t p2m_host_list(p2m_handle h, int64_t site, int32_t* out_tris, int64_t cap
     const int32_t b = h->H.site_rec[site].list_begin, e = h->H.site_rec[site].list_end;
     *len = e - b;
     for (int64_t k = 0; k < std::min<int64_t>(cap, e - b) && out_tris; ++k)
-        out_tris[k] = h->H.list_rec[b + k].tri;
+        out_tris[k] = h->H.list_tri[b + k];
     return P2M_OK;
 }
 

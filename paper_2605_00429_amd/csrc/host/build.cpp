@@ -114,17 +114,28 @@ struct CellWork {
     std::vector<int32_t> list;
     std::vector<uint32_t> stamp;
     uint32_t gen = 0;
+    bool unresolved = false;  // a corner check gave up (budgeted cells only)
 };
 
 constexpr int kKnn = 24;
+// Sites one corner check of the first (density) pass may examine; ordinary
+// checks examine a few dozen.
+constexpr int64_t kPass1Budget = 4096;
 // Float32 input positions break exact co-sphericity at the 1e-7 level; a
 // violation smaller than this is rounding noise of a degenerate corner.
 constexpr double kCornerSlack = 1e-6;
 
-// Voronoi cell of site s (index into P) clipped to the box [blo, bhi].
-void voronoi_cell(int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo, d3 bhi, CellWork& w)
+// Voronoi cell of site s (index into P) clipped to the box [blo, bhi].  With
+// budget >= 0 each exact corner check examines at most that many sites; a
+// check that gives up leaves the cell a superset with w.unresolved set.
+// That happens at corners that nearly all sites are almost equidistant from
+// (the centre of a sphere tessellation, the axis of a cylinder), where the
+// check would otherwise scan the whole tree.
+void voronoi_cell(int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo, d3 bhi, CellWork& w,
+                  int64_t budget = -1)
 {
     const d3 ps = P[s];
+    w.unresolved = false;
     w.cell.init_box(blo - ps, bhi - ps);
     kd.knn(ps, kKnn, s, w.knn);
     w.tested.clear();
@@ -165,7 +176,11 @@ void voronoi_cell(int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo,
                 // in squared distance) is skipped: the cell then stays a
                 // superset of the exact one, and the walk's stop region and
                 // the lists are both built from this computed cell.
-                const int32_t f = kd.nearest_below(ps + x, r2 * (1.0 - kCornerSlack), w.tested);
+                const int32_t f = kd.nearest_below(ps + x, r2 * (1.0 - kCornerSlack), w.tested, nullptr, false, budget);
+                if (f == -2) {
+                    w.unresolved = true;
+                    continue;
+                }
                 if (f >= 0) w.found.push_back(f);
                 else w.verified.push_back(x);
             }
@@ -293,7 +308,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     // Cells (corners relative to the site, bounding-plane ids) of every site.
     std::vector<std::vector<d3>> cell_corners(P.size());
     std::vector<std::vector<int32_t>> cell_faces(P.size());
-    std::vector<char> cell_ok(P.size(), 0), cell_done(P.size(), 0);
+    std::vector<char> cell_ok(P.size(), 0), cell_done(P.size(), 0), unresolved(P.size(), 0);
     int64_t n_dense = 0;
     double t_vor1 = 0;
     if (o.augment && nVS >= 5) {
@@ -317,10 +332,11 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         std::vector<std::vector<std::pair<uint64_t, d3>>> tmp(nth);
         parallel_for(nVS, nth, [&](int64_t s, int tid) {
             CellWork& w = work[tid];
-            voronoi_cell((int32_t)s, P, kd, blo, bhi, w);
+            voronoi_cell((int32_t)s, P, kd, blo, bhi, w, kPass1Budget);
             cell_corners[s] = w.corners;
             cell_faces[s] = w.faces;
             cell_ok[s] = !w.cell.empty();
+            unresolved[s] = w.unresolved;
             const d3 ps = P[s];
             auto& kc = tmp[tid];
             kc.clear();
@@ -361,9 +377,13 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         std::vector<std::pair<uint64_t, Acc>> cells(maps[0].begin(), maps[0].end());
         maps.clear();
         std::sort(cells.begin(), cells.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        // every grid cell holding a mesh vertex counts, with 0 when no
+        // Voronoi vertex falls in it (a cylinder's cells are radial wedges
+        // with no vertex near the surface)
         std::vector<int64_t> counts;
         for (auto& c : cells)
             if (site_cells.count(c.first)) counts.push_back(c.second.n);
+        counts.resize(site_cells.size(), 0);
         int64_t median = 0;
         if (!counts.empty()) {
             std::nth_element(counts.begin(), counts.begin() + counts.size() / 2, counts.end());
@@ -466,6 +486,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             kda.build(aux);
             static const std::vector<int32_t> none;
             parallel_for(nVS, nth, [&](int64_t s, int) {
+                if (unresolved[s]) { cell_done[s] = 0; return; }
                 bool hit = false;
                 for (const d3& x : cell_corners[s])
                     if (!aux.empty() && kda.nearest_below(P[s] + x, norm2(x), none) >= 0) { hit = true; break; }
@@ -476,7 +497,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             for (size_t i = nVS; i < P.size(); ++i) is_aux[i] = 1;
             kd.build(P);
         } else {
-            std::fill(cell_done.begin(), cell_done.end(), 1);
+            for (int32_t s = 0; s < nVS; ++s) cell_done[s] = !unresolved[s];
         }
     }
     H.stats.t_optimize_s = secs_since(t0) - t_vor1;

@@ -38,8 +38,10 @@ struct HostStructure {
     std::vector<uint8_t> site_is_aux;
     // Adjacency entries: neighbour x, y, z and its site id (int bits).
     std::vector<float> adj;
-    // Interception-list entries, each site's list sorted by ell.
+    // Interception-list entries, each site's list sorted by ell (released
+    // after upload; list_tri keeps their caller triangle ids).
     std::vector<ListRec> list_rec;
+    std::vector<int32_t> list_tri;
     // Triangles in slot order (BVH leaf order): v0, |e1|^2 | e1, e1.e2 | e2, |e2|^2.
     std::vector<float> tri_rec;
     std::vector<int32_t> tri_user;  // slot -> caller's triangle id

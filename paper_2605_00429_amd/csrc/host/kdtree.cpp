@@ -99,7 +99,7 @@ void KdTree::knn(d3 q, int k, int32_t skip, std::vector<std::pair<double, int32_
 }
 
 int32_t KdTree::nearest_below(d3 q, double limit2, const std::vector<int32_t>& excluded,
-                              double* d2_out, bool first) const
+                              double* d2_out, bool first, int64_t max_points) const
 {
     if (nodes_.empty()) return -1;
     double best = limit2;
@@ -114,6 +114,10 @@ int32_t KdTree::nearest_below(d3 q, double limit2, const std::vector<int32_t>& e
         if (it.d2 >= best) continue;
         const Node& n = nodes_[it.node];
         if (n.left < 0) {
+            if (max_points >= 0) {
+                max_points -= n.end - n.begin;
+                if (max_points < 0) return -2;
+            }
             for (int32_t i = n.begin; i < n.end; ++i) {
                 int32_t p = idx_[i];
                 double d2 = norm2(pts_[p] - q);

@@ -18,8 +18,10 @@ public:
     // Nearest point to q with squared distance strictly below `limit2` whose
     // index is not in `excluded` (a small sorted vector).  -1 if none.  With
     // `first`, any such point (the first the search meets) is returned.
+    // With max_points >= 0 the search gives up after examining that many
+    // points and returns -2 (undecided).
     int32_t nearest_below(d3 q, double limit2, const std::vector<int32_t>& excluded,
-                          double* d2_out = nullptr, bool first = false) const;
+                          double* d2_out = nullptr, bool first = false, int64_t max_points = -1) const;
     // Exact nearest point (lowest index on exact ties).
     int32_t nearest(d3 q, double* d2_out = nullptr) const;
     // Every point with squared distance <= r2 (appended, unordered).
