@@ -214,10 +214,12 @@ struct Best {
 // the scan keeps several requests in flight despite its data-dependent exit.
 constexpr int kChunk = 4;
 
+// Scans at most `budget` entries; if the list is not done by then, *resume
+// is set to the next entry (else -1).
 template <bool kCtr>
-__device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, const int s,
-                                            unsigned long long& list_read, unsigned long long& exact,
-                                            unsigned long long& list_len)
+__device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, const int s, const int budget,
+                                            int* resume, unsigned long long& list_read,
+                                            unsigned long long& exact, unsigned long long& list_len)
 {
     const float4 sp = m.site_rec[2 * s];
     const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
@@ -227,7 +229,13 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
     Best b{kInf, -1, 0.f, 0.f};
     float dmin = kInf;
     int stop = rg.w;
+    *resume = -1;
     for (int e = rg.z; e < stop; e += kChunk) {
+        if (e - rg.z >= budget) {
+            *resume = e;
+            stop = e;
+            break;
+        }
         // sphere (c, r) and (a, ell) of kChunk entries; the rest of an entry
         // (e1, e2) shares their cache line
         float4 c[kChunk], a[kChunk];
@@ -268,6 +276,98 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
         list_len += (unsigned long long)(rg.w - rg.z);
     }
     return b;
+}
+
+// A lane scans its list alone for at most kSerialBudget entries; the lists
+// of the lanes that are not done by then (the cell of a central auxiliary
+// site holds nearly every triangle, and the triangle-inequality exit cannot
+// fire inside it) are finished by the whole wavefront, one after the other,
+// so that one lane walking thousands of entries does not hold its 63
+// neighbours idle for as long.
+constexpr int kSerialBudget = 512;
+constexpr int kWaveChunk = 2;
+
+// Argmin of (d2, list index) over the wavefront; ties go to the lower index.
+__device__ __forceinline__ Best wave_argmin(Best b)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float d2 = __shfl_xor(b.d2, off, 64);
+        const int idx = __shfl_xor(b.idx, off, 64);
+        const float v = __shfl_xor(b.v, off, 64);
+        const float w = __shfl_xor(b.w, off, 64);
+        const bool take = d2 < b.d2 || (d2 == b.d2 && (unsigned)idx < (unsigned)b.idx);
+        if (take) b = Best{d2, idx, v, w};
+    }
+    return b;
+}
+
+__device__ __forceinline__ float wave_min(float x)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fminf(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+// The rest of one query's List Search, from entry `from` on with the d_min
+// found so far, by the whole wavefront (q and the located site s are the
+// same in every lane): lane l takes entries base + l, base + 64 + l, ... of
+// each chunk; d_min is shared after every chunk, and the scan stops once
+// the chunk's last entry has ell - |q - s| >= d_min (the list is sorted by
+// ell, so no later entry can do better).  Every lane must call it.
+template <bool kCtr>
+__device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, const int s, const int from,
+                                              const float dmin0, unsigned long long& list_read,
+                                              unsigned long long& exact)
+{
+    const int lane = threadIdx.x & 63;
+    const float4 sp = m.site_rec[2 * s];
+    const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+    const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
+    const float dqs = sqrtf(wx * wx + wy * wy + wz * wz) * 1.000001f;
+    Best b{kInf, -1, 0.f, 0.f};
+    float dmin = dmin0;  // wave-uniform between chunks
+    int end = rg.w;
+    for (int base = from; base < rg.w; base += 64 * kWaveChunk) {
+        float4 c[kWaveChunk], a[kWaveChunk];
+#pragma unroll
+        for (int k = 0; k < kWaveChunk; ++k) {
+            const int idx = min(base + 64 * k + lane, rg.w - 1);
+            c[k] = m.list_rec[4 * (int64_t)idx];
+            a[k] = m.list_rec[4 * (int64_t)idx + 1];
+        }
+        float dl = fminf(dmin, sqrtf(b.d2));
+#pragma unroll
+        for (int k = 0; k < kWaveChunk; ++k) {
+            const int e = base + 64 * k + lane;
+            bool tested = false;
+            if (e < rg.w && a[k].w - dqs < dl) {
+                const float dx = q.x - c[k].x, dy = q.y - c[k].y, dz = q.z - c[k].z;
+                const float lim = dl + c[k].w;
+                if (dx * dx + dy * dy + dz * dz < lim * lim * 1.000001f) {
+                    const float4 f2 = m.list_rec[4 * (int64_t)e + 2], f3 = m.list_rec[4 * (int64_t)e + 3];
+                    float v, w;
+                    const float d2 = closest_point(q, make_float3(a[k].x, a[k].y, a[k].z),
+                                                   make_float3(f2.x, f2.y, f2.z), make_float3(f3.x, f3.y, f3.z),
+                                                   f2.w, v, w);
+                    tested = true;
+                    if (d2 < b.d2) {
+                        b = Best{d2, e, v, w};
+                        dl = fminf(dl, sqrtf(d2));
+                    }
+                }
+            }
+            if (kCtr) exact += (unsigned long long)__popcll(__ballot(tested));
+        }
+        dmin = wave_min(dl);
+        const int last = min(base + 64 * kWaveChunk, rg.w) - 1;
+        if (m.list_rec[4 * (int64_t)last + 1].w - dqs >= dmin) {
+            end = last + 1;
+            break;
+        }
+    }
+    if (kCtr) list_read += (unsigned long long)(end - from);
+    return wave_argmin(b);
 }
 
 // Exact branch-and-bound over the triangle BVH (points outside the domain box).
@@ -359,27 +459,49 @@ struct LdsAcc {
 // One query end to end: locate, list search (or fallback), outputs and,
 // when fused, the gradient.  Shared by the plain and the batched kernels so
 // that both give bitwise identical results.
+//
+// Every lane of the wavefront must call it (valid = false for a lane without
+// a query): long lists are scanned by the whole wavefront.
 template <bool kFused, bool kCtr, class Acc>
-__device__ __forceinline__ void run_query(const DevMesh& m, const int64_t iq, const int64_t i,
+__device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, const int64_t iq, const int64_t i,
                                           const float* __restrict__ qp, float* __restrict__ dist,
                                           int32_t* __restrict__ tri, float* __restrict__ closest,
                                           const float* __restrict__ gdist, float* __restrict__ grad_q,
                                           const Acc& acc, unsigned long long* __restrict__ ctr)
 {
     // the point is read at iq (its slot in qp), every output and gradient at i
-    const float3 q = make_float3(qp[3 * iq], qp[3 * iq + 1], qp[3 * iq + 2]);
+    float3 q = make_float3(0.f, 0.f, 0.f);
+    if (valid) q = make_float3(qp[3 * iq], qp[3 * iq + 1], qp[3 * iq + 2]);
     unsigned long long steps = 0, adj_read = 0, list_read = 0, exact = 0, list_len = 0, fb = 0;
     Best b{kInf, -1, 0.f, 0.f};
-    const bool finite = isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
-    if (finite) {
-        if (in_domain(m, q)) {
-            const int s = locate<kCtr>(m, q, steps, adj_read);
-            b = list_search<kCtr>(m, q, s, list_read, exact, list_len);
+    const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
+    int s = -1, resume = -1;
+    if (finite && in_domain(m, q)) {
+        s = locate<kCtr>(m, q, steps, adj_read);
+        b = list_search<kCtr>(m, q, s, kSerialBudget, &resume, list_read, exact, list_len);
+    }
+    // lists not done within the budget: finished by the whole wavefront
+    for (uint64_t todo = __ballot(resume >= 0); todo; todo &= todo - 1) {
+        const int src = __builtin_ctzll(todo);
+        const float3 qs = make_float3(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.x), src)),
+                                      __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.y), src)),
+                                      __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.z), src)));
+        const int ss = __builtin_amdgcn_readlane(s, src);
+        const int from = __builtin_amdgcn_readlane(resume, src);
+        const float d0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sqrtf(b.d2)), src));
+        unsigned long long lr = 0, ex = 0;
+        const Best r = list_search_wave<kCtr>(m, qs, ss, from, d0, lr, ex);
+        if ((int)(threadIdx.x & 63) == src) {
+            // the lane's own result holds earlier entries and wins ties
+            if (r.d2 < b.d2) b = r;
+            list_read += lr;
+            exact += ex;
         }
-        if (b.idx == -1) {
-            b = bvh_search(m, q);
-            fb = 1;
-        }
+    }
+    if (!valid) return;
+    if (finite && b.idx == -1) {
+        b = bvh_search(m, q);
+        fb = 1;
     }
     if (kCtr) {
         atomicAdd(&ctr[CTR_WALK_STEPS], steps);
@@ -475,10 +597,10 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
 {
     const int64_t per = gridDim.x / a.xcds;
     const int64_t j = xcd_block(a.xcds, per) * blockDim.x + threadIdx.x;
+    const bool valid = j < a.n;
+    const int64_t i = valid ? (a.perm ? (int64_t)a.perm[j] : j) : 0;
     if (!kFused) {
-        if (j >= a.n) return;
-        const int64_t i = a.perm ? (int64_t)a.perm[j] : j;
-        run_query<false, kCtr>(m, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, nullptr, nullptr,
+        run_query<false, kCtr>(m, valid, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, nullptr, nullptr,
                                DirectAcc{nullptr}, a.ctr);
         return;
     }
@@ -488,11 +610,8 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
     const LdsAcc acc{a.grad_v, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
     if (a.grad_v) acc.init();
     __syncthreads();
-    if (j < a.n) {
-        const int64_t i = a.perm ? (int64_t)a.perm[j] : j;
-        run_query<true, kCtr>(m, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q,
-                              acc, a.ctr);
-    }
+    run_query<true, kCtr>(m, valid, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q,
+                          acc, a.ctr);
     __syncthreads();
     if (a.grad_v) acc.flush();
 }
@@ -517,9 +636,13 @@ __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__
         const int32_t* perm = a.perm[mi];
         const DirectAcc acc{kFused ? a.grad_v[mi] : nullptr};
         const int64_t base = a.q_off[mi];
-        for (int64_t j = first + lane; j < last; j += 64) {
-            const int64_t i = base + (perm ? (int64_t)perm[j] : j);
-            run_query<kFused, false>(m, i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, acc, nullptr);
+        // wave-uniform trip count: every lane takes part in each run_query
+        for (int64_t j0 = first; j0 < last; j0 += 64) {
+            const int64_t j = j0 + lane;
+            const bool valid = j < last;
+            const int64_t i = valid ? base + (perm ? (int64_t)perm[j] : j) : 0;
+            run_query<kFused, false>(m, valid, i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, acc,
+                                     nullptr);
         }
     }
 }
