@@ -112,7 +112,12 @@ def bench_batched(args, plain_c2_mqps, stream):
     log(f"batched workload: generating {len(plan)} meshes and their points")
     cfg = gen.config_c4(plan)
     t0 = time.time()
-    meshes = [p2m.Mesh(c["V"], c["F"]) for c in cfg]
+    meshes = []
+    for k, c in enumerate(cfg):
+        t1 = time.time()
+        meshes.append(p2m.Mesh(c["V"], c["F"]))
+        log(f"  mesh {k + 1}/{len(cfg)}: {c['name']}, {len(c['F'])} triangles, {len(c['Q'])} points, "
+            f"built in {time.time() - t1:.1f}s")
     build_s = time.time() - t0
     counts = [len(c["Q"]) for c in cfg]
     n = int(sum(counts))
@@ -171,7 +176,8 @@ def bench_batched(args, plain_c2_mqps, stream):
     mq = lambda ms: round(n / (ms * 1e-3) / 1e6, 2)
     gbs = lambda per, ms: round(per / (ms * 1e-3) / 1e9, 1)
     res = {
-        "workload": f"{len(meshes)} meshes (uv sphere, capped cylinder, capped cone, torus, displaced icosphere), "
+        "workload": f"the first {len(meshes)} of a 64-mesh plan (uv sphere, capped cylinder, capped cone, torus, "
+                    "displaced icosphere): "
                     f"{n_tris} triangles, log-uniform 1e3-5e5 per mesh; {n} points, log-uniform 1e4-2e6 per "
                     "mesh, half uniform in box x1.2, half near-surface sigma 0.5% diag",
         "n_points": n, "n_triangles": n_tris, "build_s": round(build_s, 1),
@@ -195,6 +201,56 @@ def bench_batched(args, plain_c2_mqps, stream):
     return res
 
 
+def bench_ablation(args, stream):
+    """Auxiliary sites on and off (the shape of the paper's Tab. 4): list
+    Max / Avg / Queried, preprocessing seconds and query rate, on a
+    tessellated sphere with the paper's Sphere face count, a capped cylinder
+    and cone (rotational symmetry) and the organic displaced icosphere, for
+    1M points uniform in the mesh box scaled 10x (the paper's query region)
+    and for the 50/50 uniform (box x1.2) / near-surface mix."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2605_00429_amd as p2m
+
+    meshes = [("icosphere-5", gen.icosphere(5)),
+              ("capped cylinder 256x64", gen.capped_cylinder(1.0, 2.0, 256, 64)),
+              ("capped cone 256x64", gen.capped_cone(1.0, 2.0, 256, 64)),
+              ("displaced icosphere-6", gen.displaced_icosphere(6, np.random.default_rng(2605_00429 + 5)))]
+    out = []
+    for name, (V, F) in meshes:
+        rng = np.random.default_rng(2605_00429 + 6)
+        lo, hi = gen.scaled_box(V, 10.0)
+        sets = {"box x10": gen.uniform_box(rng, 1_000_000, lo, hi)}
+        lo, hi = gen.scaled_box(V, 1.2)
+        D = float(np.linalg.norm(V.max(0) - V.min(0)))
+        sets["mix"] = np.concatenate([gen.uniform_box(rng, 500_000, lo, hi),
+                                      gen.near_surface(rng, 500_000, V, F, 0.005 * D)]).astype(np.float32)
+        for aug in (0, 1):
+            t0 = time.time()
+            m = p2m.Mesh(V, F, augment=aug)
+            pre = time.time() - t0
+            st = m.stats()
+            row = {"mesh": name, "faces": len(F), "augment": aug, "aux_sites": st["n_aux_sites"],
+                   "pre_s": round(pre, 2), "list_max": st["list_max"], "list_avg": round(st["list_avg"], 1)}
+            for key, Q in sets.items():
+                q = torch.from_numpy(np.ascontiguousarray(Q, dtype=np.float32)).cuda()
+                n = len(q)
+                _, _, _, ctr = p2m.query_counters(m, q)
+                d = torch.empty(n, device=q.device)
+                t = torch.empty(n, dtype=torch.int32, device=q.device)
+                c = torch.empty((n, 3), device=q.device)
+                ms = timed(lambda: p2m.lib().p2m_query(m.handle, p2m._ptr(q), n, p2m._ptr(d), p2m._ptr(t),
+                                                        p2m._ptr(c), p2m._stream(stream)), 5, 2, stream)
+                row[f"queried[{key}]"] = round(ctr["list_len"] / n, 1)
+                row[f"mqps[{key}]"] = round(n / (ms * 1e-3) / 1e6, 1)
+            log(f"ablation {row}")
+            out.append(row)
+            del m
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -205,7 +261,11 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward timings")
     ap.add_argument("--cpu-sample", type=int, default=16000)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-mesh measurement")
-    ap.add_argument("--batched-meshes", type=int, default=64, help="meshes of the batched workload")
+    ap.add_argument("--batched-meshes", type=int, default=11,
+                    help="meshes of the batched workload: the first k of its 64-mesh plan (all 64 take "
+                         "about 9 minutes of host preprocessing on 16 threads)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="add the augmentation ablation (with and without auxiliary sites) on symmetric meshes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy, the reference kernel for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
@@ -377,6 +437,9 @@ def main():
 
     if not args.no_batched:
         result["batched"] = bench_batched(args, mqps, stream)
+
+    if args.ablation:
+        result["ablation"] = bench_ablation(args, stream)
 
     if not args.no_cpu_baseline:
         import oracle

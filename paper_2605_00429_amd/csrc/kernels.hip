@@ -618,11 +618,29 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
 
 // Persistent batched kernel: each wavefront takes work items (up to `tile`
 // consecutive sorted queries of one mesh) from a global counter until none
-// is left, so meshes of very different sizes share one launch.
+// is left, so meshes of very different sizes share one launch.  Fused, each
+// wavefront combines the vertex gradients of its 64 queries in its own LDS
+// hash table (kWaveSlots slots, at least 4/3 of the 192 contributions) and
+// flushes it to the current mesh's dL/dV after every round of 64.
+constexpr int kWaveSlots = 256;
+
 template <bool kFused>
 __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__ meshes, const BatchArgs a)
 {
     const int lane = threadIdx.x & 63;
+    extern __shared__ int wave_smem[];
+    int* wkeys = wave_smem + (threadIdx.x >> 6) * (4 * kWaveSlots);
+    float* wval = (float*)(wkeys + kWaveSlots);
+    if (kFused) {
+        for (int k = lane; k < kWaveSlots; k += 64) {
+            wkeys[k] = -1;
+            wval[3 * k] = 0.f;
+            wval[3 * k + 1] = 0.f;
+            wval[3 * k + 2] = 0.f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
     for (;;) {
         unsigned t = 0;
         if (lane == 0) t = atomicAdd(a.counter, 1u);
@@ -634,7 +652,8 @@ __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__
         const int64_t last = min(first + (int64_t)a.tile, count);
         const DevMesh m = meshes[mi];
         const int32_t* perm = a.perm[mi];
-        const DirectAcc acc{kFused ? a.grad_v[mi] : nullptr};
+        float* gv = kFused ? a.grad_v[mi] : nullptr;
+        const LdsAcc acc{gv, wkeys, wval, kWaveSlots};
         const int64_t base = a.q_off[mi];
         // wave-uniform trip count: every lane takes part in each run_query
         for (int64_t j0 = first; j0 < last; j0 += 64) {
@@ -643,6 +662,22 @@ __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__
             const int64_t i = valid ? base + (perm ? (int64_t)perm[j] : j) : 0;
             run_query<kFused, false>(m, valid, i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, acc,
                                      nullptr);
+            if (kFused && gv) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                for (int k = lane; k < kWaveSlots; k += 64) {
+                    const int key = wkeys[k];
+                    if (key >= 0) {
+                        DirectAcc{gv}.add(key, wval[3 * k], wval[3 * k + 1], wval[3 * k + 2]);
+                        wkeys[k] = -1;
+                        wval[3 * k] = 0.f;
+                        wval[3 * k + 1] = 0.f;
+                        wval[3 * k + 2] = 0.f;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
         }
     }
 }
@@ -1018,7 +1053,7 @@ hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, int bits,
 hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int block, bool fused,
                         hipStream_t st)
 {
-    if (fused) batch_kernel<true><<<grid, block, 0, st>>>(meshes, a);
+    if (fused) batch_kernel<true><<<grid, block, (size_t)(block / 64) * kWaveSlots * 16, st>>>(meshes, a);
     else batch_kernel<false><<<grid, block, 0, st>>>(meshes, a);
     return hipGetLastError();
 }
