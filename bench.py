@@ -399,6 +399,15 @@ def main():
                                               "list_nnz", "device_bytes")}
     result["build_s"] = round(build_s, 2)
 
+    # mesh-to-mesh building block: the same points reduced on the device to
+    # max / argmax / sums (one-sided Hausdorff distance and Chamfer term)
+    red = torch.empty(5, dtype=torch.float64, device=dev)
+    ms_red = timed(lambda: p2m.lib().p2m_point_set_distance(mesh.handle, p2m._ptr(q), n, p2m._ptr(red),
+                                                            p2m._stream(stream)), args.steps, args.warmup, stream)
+    result["point_set_distance"] = {"ms": round(ms_red, 4), "mqps": round(n / (ms_red * 1e-3) / 1e6, 2),
+                                    "vs_forward": round(ms_per_step / ms_red, 4)}
+    log(f"point-set distance (query + reduction): {ms_red:.3f} ms")
+
     if not args.no_grad:
         g = torch.from_numpy(np.random.default_rng(2605_00429 + 3).normal(size=n).astype(np.float32)).to(dev)
         gv = torch.zeros((len(V), 3), dtype=torch.float32, device=dev)

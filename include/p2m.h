@@ -124,6 +124,22 @@ int32_t p2m_destroy(p2m_handle h);
 int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
                   int32_t* d_out_tri, float* d_out_closest, void* stream);
 
+/* Distance from a point set to the mesh, reduced on the device: the
+ * building block of mesh-to-mesh distance (named as an application in
+ * Sec. 5).  With the points sampled on (or the vertices of) a second surface
+ * A, d_out[0] is the one-sided Hausdorff distance from A to this mesh and
+ * d_out[2] / d_out[4] the mean distance (one Chamfer term).
+ *   d_points: device, n x 3 float32
+ *   d_out:    device, 5 float64: max distance, index of the point attaining it
+ *             (lowest index on ties), sum of distances, sum of squared
+ *             distances, number of points counted; non-finite points (NaN
+ *             distance) are left out.  n = 0 (or no finite point) gives
+ *             max = -1, index = -1, sums and count 0.
+ * Runs p2m_query's sort and search into a handle-owned buffer (n floats,
+ * allocated on first use and grown as needed; same concurrency rule as
+ * p2m_query) and two reduction kernels, all on `stream`. */
+int32_t p2m_point_set_distance(p2m_handle h, const float* d_points, int64_t n, double* d_out, void* stream);
+
 /* The two halves of p2m_query, for callers that sort once and query several
  * times (or time the search kernel alone).
  * p2m_sort_points: writes to d_order (device, n int32) the order in which

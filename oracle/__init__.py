@@ -132,6 +132,26 @@ def gradient(V, F, Q, tri, g):
     return dq, dV
 
 
+def point_set_distance(V, F, P, n_threads=0):
+    """Distances of the points ``P`` to the mesh, reduced as the mesh-to-mesh
+    measures need them (Sec. 5 names mesh-to-mesh distance as an application
+    of the point query): the largest distance and the first point attaining
+    it, the FP64 sums of d and d^2 and the number of finite points (points
+    with a non-finite coordinate are left out).  ``max`` / ``argmax`` are -1
+    when no point counts."""
+    P = np.asarray(P, dtype=np.float32).reshape(-1, 3)
+    if len(P) == 0:
+        return {"max": -1.0, "argmax": -1, "sum": 0.0, "sum_sq": 0.0, "count": 0}
+    d, _, _, _ = distance(V, F, P, n_threads=n_threads, want_closest=False)
+    ok = np.isfinite(P).all(axis=1)
+    if not ok.any():
+        return {"max": -1.0, "argmax": -1, "sum": 0.0, "sum_sq": 0.0, "count": 0}
+    dd = np.where(ok, d, -np.inf)
+    k = int(np.argmax(dd))          # first index among equal maxima
+    return {"max": float(dd[k]), "argmax": k, "sum": float(d[ok].sum()), "sum_sq": float((d[ok] ** 2).sum()),
+            "count": int(ok.sum())}
+
+
 def nearest_point(P, Q):
     """Brute-force nearest of the points ``P`` for each query: ``(idx, dist)``."""
     P, Q = _f32(P), _f32(Q)

@@ -15,7 +15,8 @@ import numpy as np
 from . import _lib
 from ._lib import P2MError, check, lib
 
-__all__ = ["Mesh", "Batch", "distance", "query", "query_backward", "query_fused",
+__all__ = ["Mesh", "Batch", "distance", "query", "query_backward", "query_fused", "point_set_distance",
+           "hausdorff", "chamfer",
            "query_counters", "sort_points", "query_sorted", "query_ordered", "P2MError", "build_opts"]
 
 
@@ -190,6 +191,49 @@ def query(mesh, points, want_tri=True, want_closest=True, stream=None):
     closest = torch.empty((n, 3), dtype=torch.float32, device=p.device) if want_closest else None
     check(lib().p2m_query(mesh.handle, _ptr(p), n, _ptr(dist), _ptr(tri), _ptr(closest), _stream(stream)))
     return dist, tri, closest
+
+
+def point_set_distance(mesh, points, stream=None):
+    """Distances of a point set to ``mesh``, reduced on the device
+    (``p2m_point_set_distance``): a dict with ``max``, ``argmax`` (lowest
+    index on ties), ``sum``, ``sum_sq`` and ``count`` (non-finite points are
+    left out; ``max`` and ``argmax`` are -1 when none is counted)."""
+    import torch
+    p = _check_points(mesh, points)
+    out = torch.empty(5, dtype=torch.float64, device=p.device)
+    check(lib().p2m_point_set_distance(mesh.handle, _ptr(p), p.shape[0], _ptr(out), _stream(stream)))
+    v = out.cpu().tolist()
+    return {"max": v[0], "argmax": int(v[1]), "sum": v[2], "sum_sq": v[3], "count": int(v[4])}
+
+
+def _surface_points(mesh, points):
+    import torch
+    if points is not None:
+        return points
+    # the referenced vertices: exact vertex-to-mesh distances
+    V = mesh.V[np.unique(mesh.F)]
+    return torch.from_numpy(np.ascontiguousarray(V, dtype=np.float32)).to(mesh.device)
+
+
+def hausdorff(mesh_a, mesh_b, points_a=None, points_b=None, symmetric=True, stream=None):
+    """Hausdorff distance between two meshes measured on point sets of each
+    (``points_a`` on A, ``points_b`` on B; by default their referenced
+    vertices).  One-sided (A to B) unless ``symmetric``."""
+    ab = point_set_distance(mesh_b, _surface_points(mesh_a, points_a).to(mesh_b.device), stream)["max"]
+    if not symmetric:
+        return ab
+    ba = point_set_distance(mesh_a, _surface_points(mesh_b, points_b).to(mesh_a.device), stream)["max"]
+    return max(ab, ba)
+
+
+def chamfer(mesh_a, mesh_b, points_a=None, points_b=None, squared=False, stream=None):
+    """Chamfer distance: the mean distance from points of A to mesh B plus
+    the mean distance from points of B to mesh A (mean squared distances
+    with ``squared``)."""
+    key = "sum_sq" if squared else "sum"
+    ab = point_set_distance(mesh_b, _surface_points(mesh_a, points_a).to(mesh_b.device), stream)
+    ba = point_set_distance(mesh_a, _surface_points(mesh_b, points_b).to(mesh_a.device), stream)
+    return ab[key] / max(ab["count"], 1) + ba[key] / max(ba["count"], 1)
 
 
 def sort_points(mesh, points, want_sorted=False, stream=None):

@@ -76,6 +76,7 @@ SIGNATURES = {
                          ctypes.POINTER(_VP)]),
     "p2m_destroy": (_I32, [_VP]),
     "p2m_query": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP]),
+    "p2m_point_set_distance": (_I32, [_VP, _VP, _I64, _VP, _VP]),
     "p2m_query_backward": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "p2m_query_fused": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "p2m_get_stats": (_I32, [_VP, ctypes.POINTER(p2m_stats)]),

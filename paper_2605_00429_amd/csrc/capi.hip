@@ -53,6 +53,8 @@ struct p2m_handle_ {
     p2m_query_config cfg{256, 1, 1, 0};
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    void* rws = nullptr;  // point-set distances and reduction partials
+    size_t rws_bytes = 0;
 
     ~p2m_handle_()
     {
@@ -60,6 +62,7 @@ struct p2m_handle_ {
             DeviceGuard g(device);
             for (void* p : allocs) (void)hipFree(p);
             if (ws) (void)hipFree(ws);
+            if (rws) (void)hipFree(rws);
         }
     }
 
@@ -272,6 +275,39 @@ int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_d
 {
     return query_common(h, d_points, n, d_out_dist, d_out_tri, d_out_closest, nullptr, nullptr, nullptr,
                         nullptr, false, stream);
+}
+
+int32_t p2m_point_set_distance(p2m_handle h, const float* d_points, int64_t n, double* d_out, void* stream)
+{
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (!d_out || (n > 0 && !d_points)) return fail(P2M_ERR_INVALID_ARG, "null points or output");
+    if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
+    DeviceGuard dg(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t dist_bytes = ((size_t)n * sizeof(float) + 255) & ~(size_t)255;
+    const size_t need = dist_bytes + 5 * sizeof(double) * (size_t)p2m::reduce_blocks(n);
+    if (h->rws_bytes < need) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        if (h->rws) (void)hipFree(h->rws);
+        h->rws = nullptr;
+        h->rws_bytes = 0;
+        e = hipMalloc(&h->rws, need + need / 4);
+        if (e != hipSuccess) return fail(P2M_ERR_OOM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+        h->rws_bytes = need + need / 4;
+    }
+    float* dist = (float*)h->rws;
+    double* part = (double*)((char*)h->rws + dist_bytes);
+    if (n > 0) {
+        const int32_t rc = query_common(h, d_points, n, dist, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                        false, stream);
+        if (rc != P2M_OK) return rc;
+    }
+    const hipError_t e = p2m::launch_reduce_dist(dist, n, part, d_out, st);
+    if (e != hipSuccess) return hip_fail(e, "reduction launch");
+    return P2M_OK;
 }
 
 int32_t p2m_sort_points(p2m_handle h, const float* d_points, int64_t n, int32_t* d_order,

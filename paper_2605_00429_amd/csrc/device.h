@@ -82,6 +82,11 @@ hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, int bits,
                           const int32_t** perm_out, hipStream_t st, float* sorted_q = nullptr);
 // Where launch_reorder leaves the order inside ws (fixed for given n, bits).
 const int32_t* reorder_perm_location(void* ws, int64_t n, int bits);
+// Max (with index), sum, sum of squares and count of the non-NaN entries of
+// d[0..n): 5 doubles to out; part holds 5 doubles per block of the first
+// stage (reduce_blocks(n) blocks).
+int reduce_blocks(int64_t n);
+hipError_t launch_reduce_dist(const float* d, int64_t n, double* part, double* out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 
 }  // namespace p2m

@@ -20,6 +20,7 @@
 // (envelope theorem), scattered with float32 atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -1055,6 +1056,111 @@ hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int
 {
     if (fused) batch_kernel<true><<<grid, block, (size_t)(block / 64) * kWaveSlots * 16, st>>>(meshes, a);
     else batch_kernel<false><<<grid, block, 0, st>>>(meshes, a);
+    return hipGetLastError();
+}
+
+// Reduction of a point set's distances (the mesh-to-mesh measures built on
+// the point query): the largest distance with the lowest index among equal
+// ones, the sums of d and d^2 in FP64, and the number of non-NaN distances.
+// Stage 1 leaves 5 doubles per block; stage 2 (one block) folds them.
+constexpr int kRedBlock = 256;
+
+struct RedVal {
+    double mx, idx, sum, sum2, cnt;
+};
+
+__device__ __forceinline__ RedVal red_combine(RedVal a, const RedVal& b)
+{
+    if (b.mx > a.mx || (b.mx == a.mx && b.idx >= 0 && (a.idx < 0 || b.idx < a.idx))) {
+        a.mx = b.mx;
+        a.idx = b.idx;
+    }
+    a.sum += b.sum;
+    a.sum2 += b.sum2;
+    a.cnt += b.cnt;
+    return a;
+}
+
+__device__ __forceinline__ RedVal red_block(RedVal v)
+{
+    __shared__ double sh[5][kRedBlock];
+    sh[0][threadIdx.x] = v.mx;
+    sh[1][threadIdx.x] = v.idx;
+    sh[2][threadIdx.x] = v.sum;
+    sh[3][threadIdx.x] = v.sum2;
+    sh[4][threadIdx.x] = v.cnt;
+    __syncthreads();
+    for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const RedVal o{sh[0][threadIdx.x + w], sh[1][threadIdx.x + w], sh[2][threadIdx.x + w],
+                           sh[3][threadIdx.x + w], sh[4][threadIdx.x + w]};
+            RedVal m{sh[0][threadIdx.x], sh[1][threadIdx.x], sh[2][threadIdx.x], sh[3][threadIdx.x],
+                     sh[4][threadIdx.x]};
+            m = red_combine(m, o);
+            sh[0][threadIdx.x] = m.mx;
+            sh[1][threadIdx.x] = m.idx;
+            sh[2][threadIdx.x] = m.sum;
+            sh[3][threadIdx.x] = m.sum2;
+            sh[4][threadIdx.x] = m.cnt;
+        }
+        __syncthreads();
+    }
+    return RedVal{sh[0][0], sh[1][0], sh[2][0], sh[3][0], sh[4][0]};
+}
+
+__global__ void __launch_bounds__(kRedBlock) reduce_dist_kernel(const float* __restrict__ d, int64_t n,
+                                                                 double* __restrict__ part)
+{
+    RedVal v{-1.0, -1.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kRedBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedBlock) {
+        const float x = d[i];
+        if (x != x) continue;  // NaN: a non-finite point
+        const double xd = (double)x;
+        if (xd > v.mx) {       // indices grow along a thread's stride: the first wins
+            v.mx = xd;
+            v.idx = (double)i;
+        }
+        v.sum += xd;
+        v.sum2 += xd * xd;
+        v.cnt += 1.0;
+    }
+    const RedVal r = red_block(v);
+    if (threadIdx.x == 0) {
+        double* o = part + 5 * (int64_t)blockIdx.x;
+        o[0] = r.mx;
+        o[1] = r.idx;
+        o[2] = r.sum;
+        o[3] = r.sum2;
+        o[4] = r.cnt;
+    }
+}
+
+__global__ void __launch_bounds__(kRedBlock) reduce_final_kernel(const double* __restrict__ part, int nb,
+                                                                  double* __restrict__ out)
+{
+    RedVal v{-1.0, -1.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += kRedBlock)
+        v = red_combine(v, RedVal{part[5 * b], part[5 * b + 1], part[5 * b + 2], part[5 * b + 3], part[5 * b + 4]});
+    const RedVal r = red_block(v);
+    if (threadIdx.x == 0) {
+        out[0] = r.mx;
+        out[1] = r.idx;
+        out[2] = r.sum;
+        out[3] = r.sum2;
+        out[4] = r.cnt;
+    }
+}
+
+int reduce_blocks(int64_t n)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + kRedBlock - 1) / kRedBlock));
+}
+
+hipError_t launch_reduce_dist(const float* d, int64_t n, double* part, double* out, hipStream_t st)
+{
+    const int nb = reduce_blocks(n);
+    reduce_dist_kernel<<<nb, kRedBlock, 0, st>>>(d, n, part);
+    reduce_final_kernel<<<1, kRedBlock, 0, st>>>(part, nb, out);
     return hipGetLastError();
 }
 

@@ -321,3 +321,47 @@ def test_gradient_matches_central_differences():
             Vm[v, k] -= h
             fd = np.sum(g * (dist64(Vp, q64) - dist64(Vm, q64))) / (2 * h)
             assert abs(fd - dV[v, k]) < 1e-5 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------------------
+# Point-set reduction (mesh-to-mesh distance built on the point query)
+
+def test_point_set_distance_translated_cube_closed_form():
+    """Vertices of a cube translated by delta along x, against the cube: the
+    four at x = h + delta lie delta from the face x = h, the four at
+    x = -h + delta lie on the edges y, z = +-h of the cube (distance 0)."""
+    V, F = gen.cube(1.0)
+    for delta in (0.25, 0.5, 1.5):
+        A = (V + np.array([delta, 0.0, 0.0], np.float32)).astype(np.float32)
+        r = oracle.point_set_distance(V, F, A)
+        far = np.nonzero(np.isclose(A[:, 0], 1.0 + delta))[0]
+        assert r["count"] == 8
+        assert abs(r["max"] - delta) <= 1e-12
+        assert r["argmax"] == far.min()
+        assert abs(r["sum"] - 4 * delta) <= 1e-12
+        assert abs(r["sum_sq"] - 4 * delta * delta) <= 1e-12
+
+
+def test_point_set_distance_self_is_zero_and_nan_left_out():
+    V, F = gen.icosphere(2)
+    r = oracle.point_set_distance(V, F, V[np.unique(F)])
+    assert r["max"] <= 1e-7 and r["sum"] <= 1e-5
+    P = np.array([[2.0, 0, 0], [np.nan, 0, 0], [0, 3.0, 0]], np.float32)
+    r = oracle.point_set_distance(V, F, P)
+    assert r["count"] == 2 and r["argmax"] == 2
+    empty = oracle.point_set_distance(V, F, np.zeros((0, 3), np.float32))
+    assert empty == {"max": -1.0, "argmax": -1, "sum": 0.0, "sum_sq": 0.0, "count": 0}
+
+
+def test_point_set_distance_concentric_spheres_bounds():
+    """Vertices of a radius-2 icosphere against a unit one (convex, inscribed
+    in the unit sphere, inradius rho): every distance lies in [1, 2 - rho]."""
+    V, F = gen.icosphere(3)
+    A = (2.0 * gen.icosphere(2)[0]).astype(np.float32)
+    a, b, c = (V[F[:, k]].astype(np.float64) for k in range(3))
+    n = np.cross(b - a, c - a)
+    rho = np.min(np.abs(np.sum(n * a, axis=1)) / np.linalg.norm(n, axis=1))
+    d, _, _, _ = oracle.distance(V, F, A, want_closest=False)
+    assert d.min() >= 1.0 - 1e-6 and d.max() <= 2.0 - rho + 1e-6
+    r = oracle.point_set_distance(V, F, A)
+    assert abs(r["max"] - d.max()) == 0 and r["count"] == len(A)
