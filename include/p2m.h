@@ -74,6 +74,9 @@ typedef struct {
     float seed_cell_scale;     /* seed grid cell = this * mean edge length (2) */
     int64_t seed_max_cells;    /* cap on seed grid cells (16M) */
     int32_t n_threads;         /* host preprocessing threads, 0 = all */
+    int32_t gpu_lists;         /* 1: the list stage's sphere-union tests run on the device
+                                  (same lists; sites with more than 64 balls stay on the
+                                  host); 0: all on the host (default 1; needs device >= 0) */
     int32_t device;            /* HIP device to upload to; -2 (default) = the current
                                   device; -1 = host only (inspection, no query calls) */
 } p2m_build_opts;

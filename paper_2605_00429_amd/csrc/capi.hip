@@ -145,6 +145,7 @@ void p2m_default_opts(p2m_build_opts* o)
     o->dense_rel = 8.0f;
     o->ring_sites = 12;
     o->aux_list_mode = 1;
+    o->gpu_lists = 1;
     o->list_inflation_rel = 1e-7f;
     o->seed_cell_scale = 2.0f;
     o->seed_max_cells = 16 << 20;
@@ -162,7 +163,6 @@ int32_t p2m_build(const p2m_mesh_desc* mesh, const p2m_build_opts* opts, p2m_han
     p2m_handle h = nullptr;
     try {
         h = new p2m_handle_();
-        p2m::build_host(*mesh, o, h->H);
         int dev = o.device;
         if (dev == -2) {
             hipError_t e = hipGetDevice(&dev);
@@ -177,8 +177,12 @@ int32_t p2m_build(const p2m_mesh_desc* mesh, const p2m_build_opts* opts, p2m_han
                 delete h;
                 return fail(P2M_ERR_HIP, "cannot select HIP device " + std::to_string(dev));
             }
+            const p2m::GpuListFn on_device = p2m::gpu_build_lists;
+            p2m::build_host(*mesh, o, h->H, o.gpu_lists ? &on_device : nullptr);
             h->device = dev;
             h->upload_all();
+        } else {
+            p2m::build_host(*mesh, o, h->H);
         }
         h->H.stats.device_bytes = h->device_bytes;
         // The host keeps only the triangle id of each list entry (for the

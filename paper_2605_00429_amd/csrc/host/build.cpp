@@ -216,7 +216,7 @@ void check_mesh(const p2m_mesh_desc& m)
 
 }  // namespace
 
-void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructure& H)
+void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructure& H, const GpuListFn* gpu)
 {
     const auto t_start = clk::now();
     check_mesh(mesh);
@@ -523,6 +523,16 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     t0 = clk::now();
     std::vector<std::vector<int32_t>> nbr(nS), lists(nS);
     std::vector<char> bad(nS, 0);
+    std::vector<std::vector<Ball>> dev_balls(gpu ? nS : 0);
+    auto host_list = [&](CellWork& w, const std::vector<Ball>& balls, std::vector<int32_t>& out) {
+        w.list.clear();
+        if (++w.gen == 0) {
+            std::fill(w.stamp.begin(), w.stamp.end(), 0);
+            w.gen = 1;
+        }
+        bvh.query_union(balls, w.list, w.stamp, w.gen);
+        out = w.list;
+    };
     parallel_for(nS, nth, [&](int64_t s, int tid) {
         CellWork& w = work[tid];
         if (!cell_ok[s]) { bad[s] = 1; return; }
@@ -557,15 +567,36 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             }
             w.balls.resize(k);
         }
-        w.list.clear();
-        if (++w.gen == 0) {
-            std::fill(w.stamp.begin(), w.stamp.end(), 0);
-            w.gen = 1;
+        if (gpu && !w.balls.empty() && w.balls.size() <= 64) {
+            dev_balls[s] = w.balls;  // tested on the device below
+            return;
         }
-        bvh.query_union(w.balls, w.list, w.stamp, w.gen);
-        lists[s] = w.list;
-        if (w.list.empty()) bad[s] = 2;
+        host_list(w, w.balls, lists[s]);
+        if (lists[s].empty()) bad[s] = 2;
     }, 16);
+    if (gpu) {
+        GpuListJob job;
+        job.tri = &T;
+        job.bvh = &bvh;
+        job.ball_off.push_back(0);
+        for (int32_t s = 0; s < nS; ++s) {
+            if (dev_balls[s].empty()) continue;
+            job.sites.push_back(s);
+            for (const Ball& b : dev_balls[s]) job.balls.insert(job.balls.end(), {b.c.x, b.c.y, b.c.z, b.r});
+            job.ball_off.push_back((int64_t)job.balls.size() / 4);
+        }
+        std::vector<int64_t> off;
+        std::vector<int32_t> ids;
+        std::vector<char> redo;
+        (*gpu)(job, off, ids, redo);
+        parallel_for((int64_t)job.sites.size(), nth, [&](int64_t i, int tid) {
+            const int32_t s = job.sites[i];
+            if (redo[i]) host_list(work[tid], dev_balls[s], lists[s]);
+            else lists[s].assign(ids.begin() + off[i], ids.begin() + off[i + 1]);
+            std::vector<Ball>().swap(dev_balls[s]);
+            if (lists[s].empty()) bad[s] = 2;
+        }, 256);
+    }
     for (int32_t s = 0; s < nS; ++s)
         if (bad[s]) throw Error(P2M_ERR_INTERNAL, std::string(bad[s] == 1 ? "empty Voronoi cell" : "empty interception list") +
                                                       " at site " + std::to_string(s));

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 #include "common.h"
@@ -61,7 +62,31 @@ struct HostStructure {
     p2m_stats stats{};
 };
 
-// Throws p2m::Error on invalid input.
-void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& opts, HostStructure& out);
+class Bvh;
+
+// The sphere-union tests of the list stage, handed to a device: for each
+// site in `sites`, its balls (4 doubles each: centre, radius) in
+// balls[4 * ball_off[i] .. 4 * ball_off[i + 1]), at most 64 per site.
+struct GpuListJob {
+    const std::vector<d3>* tri = nullptr;  // 3 vertices per triangle (FP64)
+    const Bvh* bvh = nullptr;
+    std::vector<int32_t> sites;
+    std::vector<int64_t> ball_off;
+    std::vector<double> balls;
+};
+// Fills CSR lists (off, ids) for job.sites; redo[i] asks the host to build
+// site i's list itself.  Throws p2m::Error.
+using GpuListFn = std::function<void(const GpuListJob&, std::vector<int64_t>& off, std::vector<int32_t>& ids,
+                                     std::vector<char>& redo)>;
+
+// Throws p2m::Error on invalid input.  With `gpu`, the list stage's
+// sphere-union tests run through it (sites with more than 64 balls stay on
+// the host); the lists are the same.
+void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& opts, HostStructure& out,
+                const GpuListFn* gpu = nullptr);
+
+// The device implementation of GpuListFn (current HIP device).
+void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vector<int32_t>& ids,
+                     std::vector<char>& redo);
 
 }  // namespace p2m

@@ -1,0 +1,266 @@
+// Interception lists on the GPU (Sec. 3.3): for every site, the triangles
+// that meet the union of its balls (the corner balls of Eq. (3), or the
+// single sphere of Eq. (8)), by a traversal of the mesh BVH.
+//
+// The host computes the Voronoi cells and the balls; this file takes over
+// the sphere-union tests.  It reproduces the host's traversal exactly: the
+// same BVH, the same 64-ball masks, the same box and triangle-box
+// prefilters and the same FP64 point-triangle distance, evaluated in the
+// same operation order with no contraction into fused multiply-adds, so
+// both paths give identical lists (in identical order).
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host/build.h"
+#include "host/bvh.h"
+
+namespace p2m {
+namespace {
+
+struct GNode {
+    double lo[3], hi[3];
+    int32_t a;  // internal: left child (next node); leaf: first slot of the BVH order
+    int32_t b;  // internal: right child; leaf: -count
+};
+
+struct G3 {
+    double x, y, z;
+};
+__device__ __forceinline__ G3 gsub(G3 a, G3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ G3 gadd(G3 a, G3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ G3 gmul(G3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ double gdot(G3 a, G3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ double gmax3(double a, double b, double c)
+{
+    // the host takes std::max of {a, b, c}: the first of equal maxima
+    double m = a;
+    if (m < b) m = b;
+    if (m < c) m = c;
+    return m;
+}
+
+// Squared distance from q to triangle (a, b, c) by its vertex, edge and face
+// regions (Ericson, Real-Time Collision Detection, Sec. 5.1.5), the
+// operations in the host's order.
+__device__ double tri_dist2(G3 q, G3 a, G3 b, G3 c)
+{
+    const G3 ab = gsub(b, a), ac = gsub(c, a), ap = gsub(q, a);
+    const double d1 = gdot(ab, ap), d2 = gdot(ac, ap);
+    double u = 1, v = 0, w = 0;
+    if (d1 <= 0 && d2 <= 0) {
+        u = 1; v = 0; w = 0;
+    } else {
+        const G3 bp = gsub(q, b);
+        const double d3v = gdot(ab, bp), d4 = gdot(ac, bp);
+        const G3 cp = gsub(q, c);
+        const double d5 = gdot(ab, cp), d6 = gdot(ac, cp);
+        const double vc = d1 * d4 - d3v * d2;
+        const double vb = d5 * d2 - d1 * d6;
+        const double va = d3v * d6 - d5 * d4;
+        if (d3v >= 0 && d4 <= d3v) {
+            u = 0; v = 1; w = 0;
+        } else if (vc <= 0 && d1 >= 0 && d3v <= 0) {
+            const double t = d1 / (d1 - d3v);
+            u = 1 - t; v = t; w = 0;
+        } else if (d6 >= 0 && d5 <= d6) {
+            u = 0; v = 0; w = 1;
+        } else if (vb <= 0 && d2 >= 0 && d6 <= 0) {
+            const double t = d2 / (d2 - d6);
+            u = 1 - t; v = 0; w = t;
+        } else if (va <= 0 && (d4 - d3v) >= 0 && (d5 - d6) >= 0) {
+            const double t = (d4 - d3v) / ((d4 - d3v) + (d5 - d6));
+            u = 0; v = 1 - t; w = t;
+        } else {
+            const double den = va + vb + vc;
+            if (den > 0 && isfinite(den)) {
+                v = vb / den; w = vc / den; u = 1 - v - w;
+            } else {
+                // zero-area triangle: best of the three edges
+                double tt[3], ee[3];
+                const G3 s0[3] = {a, b, c}, s1[3] = {b, c, a};
+                for (int k = 0; k < 3; ++k) {
+                    const G3 e = gsub(s1[k], s0[k]);
+                    const double L = gdot(e, e);
+                    double t = 0.0;
+                    if (L > 0) {
+                        t = gdot(gsub(q, s0[k]), e) / L;
+                        t = t < 0.0 ? 0.0 : (1.0 < t ? 1.0 : t);
+                    }
+                    tt[k] = t;
+                    const G3 r = gsub(q, gadd(s0[k], gmul(e, t)));
+                    ee[k] = gdot(r, r);
+                }
+                if (ee[0] <= ee[1] && ee[0] <= ee[2]) { u = 1 - tt[0]; v = tt[0]; w = 0; }
+                else if (ee[1] <= ee[2]) { u = 0; v = 1 - tt[1]; w = tt[1]; }
+                else { u = tt[2]; v = 0; w = 1 - tt[2]; }
+            }
+        }
+    }
+    const G3 p = gadd(gadd(gmul(a, u), gmul(b, v)), gmul(c, w));
+    const G3 r = gsub(q, p);
+    return gdot(r, r);
+}
+
+constexpr int kStack = 64;
+
+// One site per thread.  Pass 1 (kFill = false) counts, pass 2 writes the
+// triangle ids from off[site].  A traversal that would overflow its stack
+// (never for a BVH of at most 2^29 triangles) reports count -1, and the
+// host builds that list itself.
+template <bool kFill>
+__global__ void __launch_bounds__(256) list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order,
+                                                    const double* __restrict__ T, const int64_t* __restrict__ ball_off,
+                                                    const double* __restrict__ balls, int64_t n_sites,
+                                                    int64_t* __restrict__ counts, const int64_t* __restrict__ off,
+                                                    int32_t* __restrict__ ids)
+{
+    const int64_t si = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= n_sites) return;
+    const int64_t b0 = ball_off[si];
+    const int nb = (int)(ball_off[si + 1] - b0);
+    if (kFill && counts[si] < 0) return;
+    const double* B = balls + 4 * b0;
+    int64_t cnt = 0;
+    int64_t w = kFill ? off[si] : 0;
+    struct Item {
+        int32_t node;
+        uint64_t mask;
+    } stack[kStack];
+    int sp = 0;
+    if (nb > 0) stack[sp++] = {0, nb == 64 ? ~0ULL : ((1ULL << nb) - 1)};
+    bool overflow = false;
+    while (sp > 0) {
+        const Item it = stack[--sp];
+        const GNode n = nodes[it.node];
+        uint64_t m = 0;
+        for (uint64_t r = it.mask; r; r &= r - 1) {
+            const int k = __builtin_ctzll(r);
+            const double cx = B[4 * k], cy = B[4 * k + 1], cz = B[4 * k + 2], rr = B[4 * k + 3];
+            const double dx = gmax3(n.lo[0] - cx, 0.0, cx - n.hi[0]);
+            const double dy = gmax3(n.lo[1] - cy, 0.0, cy - n.hi[1]);
+            const double dz = gmax3(n.lo[2] - cz, 0.0, cz - n.hi[2]);
+            if (dx * dx + dy * dy + dz * dz <= rr * rr) m |= 1ULL << k;
+        }
+        if (!m) continue;
+        if (n.b < 0) {
+            for (int32_t i = n.a; i < n.a - n.b; ++i) {
+                const int32_t t = order[i];
+                const G3 a{T[9 * (int64_t)t], T[9 * (int64_t)t + 1], T[9 * (int64_t)t + 2]};
+                const G3 b{T[9 * (int64_t)t + 3], T[9 * (int64_t)t + 4], T[9 * (int64_t)t + 5]};
+                const G3 c{T[9 * (int64_t)t + 6], T[9 * (int64_t)t + 7], T[9 * (int64_t)t + 8]};
+                const G3 lo{fmin(a.x, fmin(b.x, c.x)), fmin(a.y, fmin(b.y, c.y)), fmin(a.z, fmin(b.z, c.z))};
+                const G3 hi{fmax(a.x, fmax(b.x, c.x)), fmax(a.y, fmax(b.y, c.y)), fmax(a.z, fmax(b.z, c.z))};
+                for (uint64_t r = m; r; r &= r - 1) {
+                    const int k = __builtin_ctzll(r);
+                    const G3 q{B[4 * k], B[4 * k + 1], B[4 * k + 2]};
+                    const double r2 = B[4 * k + 3] * B[4 * k + 3];
+                    const double dx = gmax3(lo.x - q.x, 0.0, q.x - hi.x);
+                    const double dy = gmax3(lo.y - q.y, 0.0, q.y - hi.y);
+                    const double dz = gmax3(lo.z - q.z, 0.0, q.z - hi.z);
+                    if (dx * dx + dy * dy + dz * dz > r2) continue;
+                    if (tri_dist2(q, a, b, c) <= r2) {
+                        if (kFill) ids[w] = t;
+                        ++w;
+                        ++cnt;
+                        break;
+                    }
+                }
+            }
+            continue;
+        }
+        if (sp + 2 > kStack) {
+            overflow = true;
+            break;
+        }
+        stack[sp++] = {n.b, m};
+        stack[sp++] = {it.node + 1, m};
+    }
+    if (!kFill) counts[si] = overflow ? -1 : cnt;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    template <typename T>
+    T* get() const { return (T*)p; }
+};
+
+void check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) throw Error(P2M_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+void upload(DevBuf& b, const T* src, size_t n)
+{
+    check(hipMalloc(&b.p, n ? n * sizeof(T) : 16), "hipMalloc (list build)");
+    if (n) check(hipMemcpy(b.p, src, n * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy (list build)");
+}
+
+}  // namespace
+
+// Lists of job.sites on the current device, as CSR (off, ids); redo[i] is
+// set for a site whose list the host must build.  The host's min / max of
+// doubles (std::min / std::max on finite coordinates) equal fmin / fmax.
+void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vector<int32_t>& ids,
+                     std::vector<char>& redo)
+{
+    const int64_t ns = (int64_t)job.sites.size();
+    off.assign(ns + 1, 0);
+    ids.clear();
+    redo.clear();
+    if (ns == 0) return;
+    const std::vector<Bvh::Node>& nodes = job.bvh->nodes();
+    std::vector<GNode> gn(nodes.size());
+    for (size_t i = 0; i < nodes.size(); ++i) {
+        const Bvh::Node& n = nodes[i];
+        gn[i] = GNode{{n.lo.x, n.lo.y, n.lo.z}, {n.hi.x, n.hi.y, n.hi.z}, n.left_or_begin, n.right_or_count};
+    }
+    const std::vector<d3>& tri = *job.tri;
+    std::vector<double> T(3 * tri.size());
+    for (size_t i = 0; i < tri.size(); ++i) {
+        T[3 * i] = tri[i].x;
+        T[3 * i + 1] = tri[i].y;
+        T[3 * i + 2] = tri[i].z;
+    }
+    DevBuf d_nodes, d_order, d_T, d_boff, d_balls, d_counts, d_off, d_ids;
+    upload(d_nodes, gn.data(), gn.size());
+    upload(d_order, job.bvh->order().data(), job.bvh->order().size());
+    upload(d_T, T.data(), T.size());
+    upload(d_boff, job.ball_off.data(), job.ball_off.size());
+    upload(d_balls, job.balls.data(), job.balls.size());
+    check(hipMalloc(&d_counts.p, ns * sizeof(int64_t)), "hipMalloc (list build)");
+    const int block = 256;
+    const int grid = (int)((ns + block - 1) / block);
+    list_kernel<false><<<grid, block>>>(d_nodes.get<GNode>(), d_order.get<int32_t>(), d_T.get<double>(),
+                                        d_boff.get<int64_t>(), d_balls.get<double>(), ns, d_counts.get<int64_t>(),
+                                        nullptr, nullptr);
+    check(hipGetLastError(), "list count launch");
+    std::vector<int64_t> counts(ns);
+    check(hipMemcpy(counts.data(), d_counts.p, ns * sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy (counts)");
+    for (int64_t i = 0; i < ns; ++i) off[i + 1] = off[i] + (counts[i] > 0 ? counts[i] : 0);
+    const int64_t total = off[ns];
+    upload(d_off, off.data(), off.size());
+    check(hipMalloc(&d_ids.p, total ? total * sizeof(int32_t) : 16), "hipMalloc (list build)");
+    list_kernel<true><<<grid, block>>>(d_nodes.get<GNode>(), d_order.get<int32_t>(), d_T.get<double>(),
+                                       d_boff.get<int64_t>(), d_balls.get<double>(), ns, d_counts.get<int64_t>(),
+                                       d_off.get<int64_t>(), d_ids.get<int32_t>());
+    check(hipGetLastError(), "list fill launch");
+    ids.resize(total);
+    if (total)
+        check(hipMemcpy(ids.data(), d_ids.p, total * sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy (lists)");
+    // a count of -1 marks a list the host must build (its range is empty)
+    redo.assign(ns, 0);
+    for (int64_t i = 0; i < ns; ++i) redo[i] = counts[i] < 0;
+}
+
+}  // namespace p2m
