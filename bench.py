@@ -261,6 +261,9 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the forward+backward timings")
     ap.add_argument("--cpu-sample", type=int, default=16000)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-mesh measurement")
+    ap.add_argument("--no-point-set", action="store_true",
+                    help="skip the point-set distance measurement (profiling runs: it launches the search "
+                         "kernel with fewer outputs)")
     ap.add_argument("--batched-meshes", type=int, default=11,
                     help="meshes of the batched workload: the first k of its 64-mesh plan (all 64 take "
                          "about 9 minutes of host preprocessing on 16 threads)")
@@ -402,11 +405,12 @@ def main():
     # mesh-to-mesh building block: the same points reduced on the device to
     # max / argmax / sums (one-sided Hausdorff distance and Chamfer term)
     red = torch.empty(5, dtype=torch.float64, device=dev)
-    ms_red = timed(lambda: p2m.lib().p2m_point_set_distance(mesh.handle, p2m._ptr(q), n, p2m._ptr(red),
+    ms_red = None if args.no_point_set else timed(lambda: p2m.lib().p2m_point_set_distance(mesh.handle, p2m._ptr(q), n, p2m._ptr(red),
                                                             p2m._stream(stream)), args.steps, args.warmup, stream)
-    result["point_set_distance"] = {"ms": round(ms_red, 4), "mqps": round(n / (ms_red * 1e-3) / 1e6, 2),
-                                    "vs_forward": round(ms_per_step / ms_red, 4)}
-    log(f"point-set distance (query + reduction): {ms_red:.3f} ms")
+    if ms_red is not None:
+        result["point_set_distance"] = {"ms": round(ms_red, 4), "mqps": round(n / (ms_red * 1e-3) / 1e6, 2),
+                                        "vs_forward": round(ms_per_step / ms_red, 4)}
+        log(f"point-set distance (query + reduction): {ms_red:.3f} ms")
 
     if not args.no_grad:
         g = torch.from_numpy(np.random.default_rng(2605_00429 + 3).normal(size=n).astype(np.float32)).to(dev)
