@@ -267,6 +267,8 @@ def main():
     ap.add_argument("--batched-meshes", type=int, default=11,
                     help="meshes of the batched workload: the first k of its 64-mesh plan (all 64 take "
                          "about 9 minutes of host preprocessing on 16 threads)")
+    ap.add_argument("--octree", action="store_true",
+                    help="add the octree decomposition (leaf boxes instead of Voronoi cells) on the same workload")
     ap.add_argument("--ablation", action="store_true",
                     help="add the augmentation ablation (with and without auxiliary sites) on symmetric meshes")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -450,6 +452,23 @@ def main():
 
     if not args.no_batched:
         result["batched"] = bench_batched(args, mqps, stream)
+
+    if args.octree:
+        t0 = time.time()
+        mo = p2m.Mesh(V, F, decomposition=1, octree_max_list=512, octree_max_depth=8)
+        ob = time.time() - t0
+        so = mo.stats()
+        _, _, _, ctr_o = p2m.query_counters(mo, q)
+        ms_o = timed(lambda: p2m.lib().p2m_query(mo.handle, p2m._ptr(q), n, p2m._ptr(out[0]), p2m._ptr(out[1]),
+                                                  p2m._ptr(out[2]), p2m._stream(stream)), args.steps, args.warmup, stream)
+        result["octree"] = {"max_list": 512, "max_depth": 8, "leaves": so["n_sites"], "list_avg": round(so["list_avg"], 1),
+                            "list_nnz": so["list_nnz"], "device_bytes": so["device_bytes"], "build_s": round(ob, 1),
+                            "queried": round(ctr_o["list_len"] / n, 1), "list_read": round(ctr_o["list_read"] / n, 1),
+                            "exact_tests": round(ctr_o["exact_tests"] / n, 2), "descent_steps": round(ctr_o["walk_steps"] / n, 2),
+                            "ms": round(ms_o, 4), "mqps": round(n / (ms_o * 1e-3) / 1e6, 2),
+                            "vs_voronoi": round(ms_per_step / ms_o, 4)}
+        log(f"octree: {result['octree']}")
+        del mo
 
     if args.ablation:
         result["ablation"] = bench_ablation(args, stream)

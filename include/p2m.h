@@ -74,6 +74,13 @@ typedef struct {
     float seed_cell_scale;     /* seed grid cell = this * mean edge length (2) */
     int64_t seed_max_cells;    /* cap on seed grid cells (16M) */
     int32_t n_threads;         /* host preprocessing threads, 0 = all */
+    int32_t decomposition;     /* convex cells of the domain: 0 = Voronoi cells of the sites
+                                  (the paper's, default); 1 = an adaptive octree over the mesh
+                                  box x1.25 whose leaf boxes get corner-ball lists about the
+                                  mesh point closest to their centre (the paper's remark that
+                                  any convex decomposition with point location serves) */
+    int32_t octree_max_list;   /* octree: split a box while its list is longer (64) */
+    int32_t octree_max_depth;  /* octree: at most this many levels below the root (12, <= 16) */
     int32_t gpu_lists;         /* 1: the list stage's sphere-union tests run on the device
                                   (same lists; sites with more than 64 balls stay on the
                                   host); 0: all on the host (default 1; needs device >= 0) */

@@ -36,7 +36,9 @@ class p2m_build_opts(ctypes.Structure):
                 ("dense_rel", ctypes.c_float), ("ring_sites", ctypes.c_int32),
                 ("aux_list_mode", ctypes.c_int32), ("list_inflation_rel", ctypes.c_float),
                 ("seed_cell_scale", ctypes.c_float), ("seed_max_cells", ctypes.c_int64),
-                ("n_threads", ctypes.c_int32), ("gpu_lists", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("n_threads", ctypes.c_int32), ("decomposition", ctypes.c_int32),
+                ("octree_max_list", ctypes.c_int32), ("octree_max_depth", ctypes.c_int32),
+                ("gpu_lists", ctypes.c_int32), ("device", ctypes.c_int32)]
 
 
 class p2m_stats(ctypes.Structure):

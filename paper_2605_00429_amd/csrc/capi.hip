@@ -98,6 +98,8 @@ struct p2m_handle_ {
         dm.tri_slot = upload<int32_t>(slot.data(), slot.size() * 4);
         dm.seed = upload<int32_t>(h.seed.data(), h.seed.size() * 4);
         dm.bvh = upload<float4>(h.bvh.data(), h.bvh.size() * 4);
+        dm.oct = h.oct.empty() ? nullptr : upload<int32_t>(h.oct.data(), h.oct.size() * 4);
+        for (int k = 0; k < 4; ++k) dm.oroot[k] = h.oroot[k];
         for (int k = 0; k < 3; ++k) {
             dm.gdim[k] = h.gdim[k];
             dm.gorg[k] = h.gorg[k];
@@ -146,6 +148,9 @@ void p2m_default_opts(p2m_build_opts* o)
     o->ring_sites = 12;
     o->aux_list_mode = 1;
     o->gpu_lists = 1;
+    o->decomposition = 0;
+    o->octree_max_list = 64;
+    o->octree_max_depth = 12;
     o->list_inflation_rel = 1e-7f;
     o->seed_cell_scale = 2.0f;
     o->seed_max_cells = 16 << 20;
@@ -480,6 +485,27 @@ int32_t p2m_host_locate(p2m_handle h, const float* pts, int64_t n, int32_t* out_
         const float qx = pts[3 * i], qy = pts[3 * i + 1], qz = pts[3 * i + 2];
         if (!std::isfinite(qx) || !std::isfinite(qy) || !std::isfinite(qz)) {
             out_site[i] = -1;
+            continue;
+        }
+        if (!H.oct.empty()) {
+            // octree: the leaf box (float32 descent, as on the device); -1 outside the root
+            const float q[3] = {qx, qy, qz};
+            float c[3] = {H.oroot[0], H.oroot[1], H.oroot[2]};
+            float hh = H.oroot[3];
+            bool inside = true;
+            for (int k = 0; k < 3; ++k) inside &= q[k] >= c[k] - hh && q[k] <= c[k] + hh;
+            int32_t v = inside ? H.oct[0] : -1;
+            while (inside && v >= 0) {
+                int mk = 0;
+                hh *= 0.5f;
+                for (int k = 0; k < 3; ++k) {
+                    const bool up = q[k] >= c[k];
+                    mk |= (int)up << k;
+                    c[k] = up ? c[k] + hh : c[k] - hh;
+                }
+                v = H.oct[v + mk];
+            }
+            out_site[i] = inside ? -v - 1 : -1;
             continue;
         }
         auto cell = [&](float v, int k) {

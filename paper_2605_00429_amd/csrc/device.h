@@ -18,6 +18,8 @@ struct DevMesh {
     const int32_t* tri_slot; // caller triangle id -> slot
     const int32_t* seed;     // seed grid (x fastest)
     const float4* bvh;       // 2 per node
+    const int32_t* oct;      // octree decomposition: nodes (first child, or -(site + 1)); null for Voronoi cells
+    float oroot[4];          // octree root centre xyz, half size
     int32_t gdim[3];
     float gorg[3];
     float ginv;              // 1 / seed cell size

@@ -33,6 +33,7 @@
 #include "bvh.h"
 #include "cell.h"
 #include "kdtree.h"
+#include "octree.h"
 
 namespace p2m {
 
@@ -221,7 +222,9 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     const auto t_start = clk::now();
     check_mesh(mesh);
     if (!(o.domain_scale >= 1.0f) || !(o.tau_scale > 0) || o.ring_sites < 0 ||
-        !(o.list_inflation_rel >= 0) || !(o.seed_cell_scale > 0) || o.seed_max_cells < 1)
+        !(o.list_inflation_rel >= 0) || !(o.seed_cell_scale > 0) || o.seed_max_cells < 1 ||
+        o.decomposition < 0 || o.decomposition > 1 || o.octree_max_list < 1 || o.octree_max_depth < 0 ||
+        o.octree_max_depth > 16)
         throw Error(P2M_ERR_INVALID_ARG, "invalid build option");
     const int nth = resolve_threads(o.n_threads);
     const int64_t nV = mesh.n_vertices, nT = mesh.n_triangles;
@@ -303,13 +306,35 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     std::vector<CellWork> work(nth);
     for (auto& w : work) w.stamp.assign(nT, 0);
 
-    // ---- pass 1 and ring-based augmentation (Sec. 3.2)
+    const bool octree = o.decomposition == 1;
     std::vector<char> is_aux(P.size(), 0);
+    std::vector<std::vector<int32_t>> nbr, lists;
+    int32_t nS = 0;
+    int64_t n_dense = 0;
+    OctreeCells oc;
+    if (octree) {
+        // ---- octree decomposition: leaves are the cells, no Voronoi stage
+        d3 olo, ohi;
+        padded_box(1.25, olo, ohi);
+        build_octree(T, bvh, olo, ohi, delta, o.octree_max_list, o.octree_max_depth, nth, oc);
+        P = oc.centre;
+        nS = (int32_t)P.size();
+        nbr.assign(nS, {});
+        lists.swap(oc.lists);
+        is_aux.assign(nS, 1);
+        std::fill(H.site_of_vertex.begin(), H.site_of_vertex.end(), -1);
+        // queries outside the root cube take the BVH fallback
+        for (int k = 0; k < 3; ++k) {
+            H.dlo[k] = oc.root[k] - oc.root[3];
+            H.dhi[k] = oc.root[k] + oc.root[3];
+        }
+        H.stats.t_lists_s = secs_since(t0);
+    } else {
+    // ---- pass 1 and ring-based augmentation (Sec. 3.2)
     // Cells (corners relative to the site, bounding-plane ids) of every site.
     std::vector<std::vector<d3>> cell_corners(P.size());
     std::vector<std::vector<int32_t>> cell_faces(P.size());
     std::vector<char> cell_ok(P.size(), 0), cell_done(P.size(), 0), unresolved(P.size(), 0);
-    int64_t n_dense = 0;
     double t_vor1 = 0;
     if (o.augment && nVS >= 5) {
         const double tau = o.tau_scale * mean_edge;
@@ -502,7 +527,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     }
     H.stats.t_optimize_s = secs_since(t0) - t_vor1;
     if (!o.augment || nVS < 5) std::fill(cell_done.begin(), cell_done.end(), 0);
-    const int32_t nS = (int32_t)P.size();
+    nS = (int32_t)P.size();
     if ((int64_t)nS > std::numeric_limits<int32_t>::max() / 2) throw Error(P2M_ERR_OOM, "too many sites");
 
     // ---- pass 2: remaining cells, then neighbours and interception lists
@@ -521,7 +546,8 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     }, 16);
     H.stats.t_voronoi_s = t_vor1 + secs_since(t0);
     t0 = clk::now();
-    std::vector<std::vector<int32_t>> nbr(nS), lists(nS);
+    nbr.assign(nS, {});
+    lists.assign(nS, {});
     std::vector<char> bad(nS, 0);
     std::vector<std::vector<Ball>> dev_balls(gpu ? nS : 0);
     auto host_list = [&](CellWork& w, const std::vector<Ball>& balls, std::vector<int32_t>& out) {
@@ -601,6 +627,8 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         if (bad[s]) throw Error(P2M_ERR_INTERNAL, std::string(bad[s] == 1 ? "empty Voronoi cell" : "empty interception list") +
                                                       " at site " + std::to_string(s));
     H.stats.t_lists_s = secs_since(t0);
+    }  // Voronoi decomposition
+    const int32_t n_vertex_sites = octree ? 0 : nVS;
 
     // ---- layout
     t0 = clk::now();
@@ -657,7 +685,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         H.tri_vid[4 * (size_t)t + 3] = 0;
     }
     H.n_sites = nS;
-    H.n_aux = nS - nVS;
+    H.n_aux = nS - n_vertex_sites;
     H.site_rec.assign(nS, SiteRec{});
     H.site_is_aux.assign(nS, 0);
     int64_t adj_nnz = 0, list_nnz = 0, adj_max = 0, list_max = 0;
@@ -748,8 +776,21 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         r[4] = round_up(n.hi.x); r[5] = round_up(n.hi.y); r[6] = round_up(n.hi.z);
         r[7] = ibits(n.right_or_count);
     }
+    if (octree) {
+        // leaf ids in the final site order; no seed grid (the descent starts at the root)
+        H.oct = oc.nodes;
+        for (int32_t& v : H.oct)
+            if (v < 0) v = -(new_id[-v - 1] + 1);
+        for (int k = 0; k < 4; ++k) H.oroot[k] = oc.root[k];
+        H.gcell = 1.0f;
+        for (int k = 0; k < 3; ++k) {
+            H.gdim[k] = 1;
+            H.gorg[k] = 0.0f;
+        }
+        H.seed.assign(1, 0);
+    }
     // seed grid over the mesh box x1.25: exact nearest site of each cell centre
-    {
+    if (!octree) {
         d3 glo, ghi;
         padded_box(1.25, glo, ghi);
         double cell = o.seed_cell_scale * mean_edge;
@@ -784,8 +825,8 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     H.stats.n_vertices = nV;
     H.stats.n_triangles = nT;
     H.stats.n_sites = nS;
-    H.stats.n_vertex_sites = nVS;
-    H.stats.n_aux_sites = nS - nVS;
+    H.stats.n_vertex_sites = n_vertex_sites;
+    H.stats.n_aux_sites = nS - n_vertex_sites;
     H.stats.n_dense_cells = n_dense;
     H.stats.adj_nnz = adj_nnz;
     H.stats.adj_max = adj_max;

@@ -56,6 +56,11 @@ struct HostStructure {
     float dlo[3] = {0, 0, 0}, dhi[3] = {0, 0, 0};
     // Fallback BVH nodes: lo xyz, a | hi xyz, b (see Bvh::Node; leaf ranges in slots).
     std::vector<float> bvh;
+    // Octree decomposition only (empty otherwise): nodes breadth first, a
+    // node holding the first of its 8 children or -(site + 1) for a leaf;
+    // root centre xyz and half size.
+    std::vector<int32_t> oct;
+    float oroot[4] = {0, 0, 0, 0};
     // Host-side views for inspection.
     std::vector<int32_t> site_of_vertex;  // caller vertex -> site id or -1
 

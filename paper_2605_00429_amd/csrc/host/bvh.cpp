@@ -68,7 +68,7 @@ double Bvh::box_d2(const Node& n, d3 q)
 }
 
 void Bvh::query_union(const std::vector<Ball>& balls, std::vector<int32_t>& out,
-                      std::vector<uint32_t>& stamp, uint32_t gen) const
+                      std::vector<uint32_t>& stamp, uint32_t gen, size_t cap) const
 {
     if (nodes_.empty() || balls.empty()) return;
     const std::vector<d3>& T = *tri_;
@@ -107,6 +107,7 @@ void Bvh::query_union(const std::vector<Ball>& balls, std::vector<int32_t>& out,
                         if (closest_on_triangle(bl.c, a, b, c, &p) <= r2) {
                             stamp[t] = gen;
                             out.push_back(t);
+                            if (out.size() > cap) return;
                             break;
                         }
                     }

@@ -5,6 +5,7 @@
 // the exact fallback of queries outside the domain box.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -27,9 +28,10 @@ public:
     // tri: 3 vertices per triangle (FP64 copies of the FP32 input).
     void build(const std::vector<d3>& tri);
     // Triangles (original ids) meeting the closed union of `balls`.  `stamp`
-    // (size >= n triangles) and `gen` deduplicate across calls.
+    // (size >= n triangles) and `gen` deduplicate across calls.  Stops as
+    // soon as `out` holds more than `cap` entries (it is then incomplete).
     void query_union(const std::vector<Ball>& balls, std::vector<int32_t>& out,
-                     std::vector<uint32_t>& stamp, uint32_t gen) const;
+                     std::vector<uint32_t>& stamp, uint32_t gen, size_t cap = SIZE_MAX) const;
     // Closest point of the mesh to q; returns squared distance.
     double closest(d3 q, int32_t* tri, d3* p) const;
     const std::vector<Node>& nodes() const { return nodes_; }

@@ -202,6 +202,26 @@ __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned
     return s;
 }
 
+// Cell Locate in the octree decomposition: descend from the root to the leaf
+// box holding q (children split at the parent's centre, q >= centre taking
+// the upper half, as the host built them; every split plane is exact in
+// float32).  The caller has checked that q lies in the root box.
+__device__ __forceinline__ int octree_locate(const DevMesh& m, const float3 q, unsigned long long& steps)
+{
+    float cx = m.oroot[0], cy = m.oroot[1], cz = m.oroot[2], h = m.oroot[3];
+    int v = m.oct[0];
+    while (v >= 0) {
+        h *= 0.5f;
+        const bool ux = q.x >= cx, uy = q.y >= cy, uz = q.z >= cz;
+        cx = ux ? cx + h : cx - h;
+        cy = uy ? cy + h : cy - h;
+        cz = uz ? cz + h : cz - h;
+        v = m.oct[v + ((int)ux | ((int)uy << 1) | ((int)uz << 2))];
+        steps += 1;
+    }
+    return -v - 1;
+}
+
 // Best triangle so far: idx >= 0 is a list entry, idx <= -2 the triangle
 // slot -(idx + 2) (fallback search), -1 none.
 struct Best {
@@ -214,6 +234,9 @@ struct Best {
 // fetched kChunk at a time (all loads issued before any is used) so that
 // the scan keeps several requests in flight despite its data-dependent exit.
 constexpr int kChunk = 4;
+// Load whole entries with the chunk (one round trip per chunk) instead of
+// the second half only for entries that pass the sphere test.
+constexpr bool kFullRecord = false;
 
 // Scans at most `budget` entries; if the list is not done by then, *resume
 // is set to the next entry (else -1).
@@ -239,12 +262,16 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
         }
         // sphere (c, r) and (a, ell) of kChunk entries; the rest of an entry
         // (e1, e2) shares their cache line
-        float4 c[kChunk], a[kChunk];
+        float4 c[kChunk], a[kChunk], g2[kChunk], g3[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const int idx = min(e + k, rg.w - 1);
             c[k] = m.list_rec[4 * (int64_t)idx];
             a[k] = m.list_rec[4 * (int64_t)idx + 1];
+            if (kFullRecord) {
+                g2[k] = m.list_rec[4 * (int64_t)idx + 2];
+                g3[k] = m.list_rec[4 * (int64_t)idx + 3];
+            }
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
@@ -258,7 +285,8 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
             const float lim = dmin + c[k].w;
             if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) continue;
             const int64_t idx = e + k;
-            const float4 f2 = m.list_rec[4 * idx + 2], f3 = m.list_rec[4 * idx + 3];
+            const float4 f2 = kFullRecord ? g2[k] : m.list_rec[4 * idx + 2];
+            const float4 f3 = kFullRecord ? g3[k] : m.list_rec[4 * idx + 3];
             float v, w;
             const float d2 = closest_point(q, make_float3(a[k].x, a[k].y, a[k].z), make_float3(f2.x, f2.y, f2.z),
                                            make_float3(f3.x, f3.y, f3.z), f2.w, v, w);
@@ -478,7 +506,7 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
     const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
     int s = -1, resume = -1;
     if (finite && in_domain(m, q)) {
-        s = locate<kCtr>(m, q, steps, adj_read);
+        s = m.oct ? octree_locate(m, q, steps) : locate<kCtr>(m, q, steps, adj_read);
         b = list_search<kCtr>(m, q, s, kSerialBudget, &resume, list_read, exact, list_len);
     }
     // lists not done within the budget: finished by the whole wavefront
