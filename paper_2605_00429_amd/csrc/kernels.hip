@@ -827,6 +827,11 @@ __global__ void __launch_bounds__(kSortBlock) radix_upsweep(const DevMesh m, con
     counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = hist[threadIdx.x];
 }
 
+// Downsweep: the tile is ranked stably by digit into LDS (per 256-key
+// round: ballots give the rank among a wavefront's lanes with the same
+// digit, per-wavefront counts order the wavefronts), then written out in
+// that order, so that consecutive threads write consecutive addresses of a
+// digit's run instead of scattering one element per digit per round.
 template <bool kFromPoints>
 __global__ void __launch_bounds__(kSortBlock) radix_downsweep(
     const DevMesh m, const float* __restrict__ qp, const uint32_t* __restrict__ keys_in,
@@ -834,25 +839,55 @@ __global__ void __launch_bounds__(kSortBlock) radix_downsweep(
     const uint32_t* __restrict__ offsets, int64_t n_tiles, uint32_t* __restrict__ keys_out,
     int32_t* __restrict__ vals_out, float* __restrict__ sorted_q)
 {
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t lkey[kSortTile];
+    __shared__ int32_t lval[kSortTile];
+    __shared__ uint32_t run[256], lstart[256], gbase[256];
     __shared__ uint32_t wcnt[kSortBlock / 64][256];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    run[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    run[tid] = 0u;
+    gbase[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
+    __syncthreads();
+    uint32_t key[kSortIters];
+    int32_t val[kSortIters];
+#pragma unroll
+    for (int it = 0; it < kSortIters; ++it) {
+        const int64_t idx = base + it * kSortBlock + tid;
+        key[it] = 0u;
+        val[it] = 0;
+        if (idx < n) {
+            key[it] = kFromPoints ? point_key(m, qp, idx, bits, sx, sy, sz) : keys_in[idx];
+            val[it] = kFromPoints ? (int32_t)idx : vals_in[idx];
+            atomicAdd(&run[(key[it] >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the tile's digit counts: the local start of each digit
+    if (wid == 0) {
+        const uint32_t v0 = run[4 * lane], v1 = run[4 * lane + 1], v2 = run[4 * lane + 2], v3 = run[4 * lane + 3];
+        const uint32_t t = v0 + v1 + v2 + v3;
+        uint32_t inc = t;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += y;
+        }
+        const uint32_t ex = inc - t;
+        lstart[4 * lane] = ex;
+        lstart[4 * lane + 1] = ex + v0;
+        lstart[4 * lane + 2] = ex + v0 + v1;
+        lstart[4 * lane + 3] = ex + v0 + v1 + v2;
+    }
+    __syncthreads();
+    run[tid] = lstart[tid];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
     for (int it = 0; it < kSortIters; ++it) {
 #pragma unroll
         for (int w = 0; w < kSortBlock / 64; ++w) wcnt[w][tid] = 0u;
         __syncthreads();
-        const int64_t idx = base + it * kSortBlock + tid;
-        const bool valid = idx < n;
-        uint32_t key = 0u;
-        int32_t val = 0;
-        if (valid) {
-            key = kFromPoints ? point_key(m, qp, idx, bits, sx, sy, sz) : keys_in[idx];
-            val = kFromPoints ? (int32_t)idx : vals_in[idx];
-        }
-        const uint32_t d = (key >> shift) & 255u;
+        const bool valid = base + it * kSortBlock + tid < n;
+        const uint32_t d = (key[it] >> shift) & 255u;
         // lanes of this wavefront holding the same digit
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -867,20 +902,29 @@ __global__ void __launch_bounds__(kSortBlock) radix_downsweep(
         if (valid) {
             uint32_t pos = run[d] + rank;
             for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
-            keys_out[pos] = key;
-            vals_out[pos] = val;
-            if (sorted_q) {
-                sorted_q[3 * (int64_t)pos] = qp[3 * (int64_t)val];
-                sorted_q[3 * (int64_t)pos + 1] = qp[3 * (int64_t)val + 1];
-                sorted_q[3 * (int64_t)pos + 2] = qp[3 * (int64_t)val + 2];
-            }
+            lkey[pos] = key[it];
+            lval[pos] = val[it];
         }
         __syncthreads();
         uint32_t add = 0u;
 #pragma unroll
         for (int w = 0; w < kSortBlock / 64; ++w) add += wcnt[w][tid];
         run[tid] += add;
-        __syncthreads();
+    }
+    __syncthreads();
+    const int cnt = (int)min((int64_t)kSortTile, n - base);
+    for (int j = tid; j < cnt; j += kSortBlock) {
+        const uint32_t k = lkey[j];
+        const int32_t v = lval[j];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t pos = gbase[d] + ((uint32_t)j - lstart[d]);
+        keys_out[pos] = k;
+        vals_out[pos] = v;
+        if (sorted_q) {
+            sorted_q[3 * (int64_t)pos] = qp[3 * (int64_t)v];
+            sorted_q[3 * (int64_t)pos + 1] = qp[3 * (int64_t)v + 1];
+            sorted_q[3 * (int64_t)pos + 2] = qp[3 * (int64_t)v + 2];
+        }
     }
 }
 
