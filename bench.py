@@ -419,11 +419,13 @@ def main():
         gv = torch.zeros((len(V), 3), dtype=torch.float32, device=dev)
         gq = torch.empty((n, 3), dtype=torch.float32, device=dev)
 
+        # forward then backward, the points sorted once for both passes
         def fwd_bwd():
             gv.zero_()
-            d, t, cl = p2m.query(mesh, q, stream=stream)
-            p2m.lib().p2m_query_backward(mesh.handle, p2m._ptr(q), n, p2m._ptr(t), None, None, p2m._ptr(g),
-                                         p2m._ptr(gq), p2m._ptr(gv), p2m._stream(stream))
+            p2m.lib().p2m_sort_points(mesh.handle, p2m._ptr(q), n, p2m._ptr(order), None, p2m._stream(stream))
+            p2m.query_ordered(mesh, q, order, out=out, stream=stream)
+            p2m.lib().p2m_query_backward_ordered(mesh.handle, p2m._ptr(q), p2m._ptr(order), n, p2m._ptr(out[1]),
+                                                 p2m._ptr(g), p2m._ptr(gq), p2m._ptr(gv), p2m._stream(stream))
 
         def fused():
             gv.zero_()

@@ -188,6 +188,15 @@ int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n,
                            const float* d_grad_dist, float* d_grad_points,
                            float* d_grad_vertices, void* stream);
 
+/* p2m_query_backward visiting the points in the caller's order (nullable:
+ * input order), e.g. the d_order p2m_sort_points wrote for the forward pass,
+ * so that the points are sorted once for both passes.  d_order must be a
+ * permutation of [0, n) (not checked); other arguments as in
+ * p2m_query_backward. */
+int32_t p2m_query_backward_ordered(p2m_handle h, const float* d_points, const int32_t* d_order, int64_t n,
+                                   const int32_t* d_tri, const float* d_grad_dist, float* d_grad_points,
+                                   float* d_grad_vertices, void* stream);
+
 /* Forward and backward in one pass when dL/dd is known up front.  Outputs as
  * in p2m_query and p2m_query_backward (d_out_tri and d_out_closest nullable). */
 int32_t p2m_query_fused(p2m_handle h, const float* d_points, int64_t n,

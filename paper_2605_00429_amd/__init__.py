@@ -297,16 +297,23 @@ def query_counters(mesh, points, stream=None):
     return dist, tri, closest, dict(zip(names, c))
 
 
-def query_backward(mesh, points, tri, grad_dist, grad_points=True, grad_vertices=None, stream=None):
+def query_backward(mesh, points, tri, grad_dist, grad_points=True, grad_vertices=None, order=None, stream=None):
     """Gradients of ``sum(grad_dist * dist)``: ``(dL/dpoints, dL/dV)``.
-    ``grad_vertices`` may be a zeroed (nV, 3) tensor to accumulate into."""
+    ``grad_vertices`` may be a zeroed (nV, 3) tensor to accumulate into.
+    ``order``: the visiting order ``sort_points`` gave for the forward pass
+    (``p2m_query_backward_ordered``); without it the points are sorted again
+    when dL/dV is wanted."""
     import torch
     p = _check_points(mesh, points)
     n = p.shape[0]
     g = grad_dist.contiguous().to(torch.float32)
     gq = torch.empty((n, 3), dtype=torch.float32, device=p.device) if grad_points else None
-    check(lib().p2m_query_backward(mesh.handle, _ptr(p), n, _ptr(tri.contiguous()), None, None, _ptr(g),
-                                   _ptr(gq), _ptr(grad_vertices), _stream(stream)))
+    if order is not None:
+        check(lib().p2m_query_backward_ordered(mesh.handle, _ptr(p), _ptr(order), n, _ptr(tri.contiguous()),
+                                               _ptr(g), _ptr(gq), _ptr(grad_vertices), _stream(stream)))
+    else:
+        check(lib().p2m_query_backward(mesh.handle, _ptr(p), n, _ptr(tri.contiguous()), None, None, _ptr(g),
+                                       _ptr(gq), _ptr(grad_vertices), _stream(stream)))
     return gq, grad_vertices
 
 
@@ -332,9 +339,13 @@ def _make_fn():
     class _P2MDistance(torch.autograd.Function):
         @staticmethod
         def forward(ctx, points, vertices, mesh):
-            dist, tri, closest = query(mesh, points.detach())
+            p = points.detach()
+            # sort once: the backward visits the points in the same order
+            order = sort_points(mesh, p) if mesh.query_config()["reorder"] else None
+            dist, tri, closest = query_ordered(mesh, p, order)
             ctx.mesh = mesh
-            ctx.save_for_backward(points.detach(), tri)
+            ctx.order = order
+            ctx.save_for_backward(p, tri)
             ctx.has_vertices = vertices is not None
             ctx.mark_non_differentiable(tri, closest)
             return dist, tri, closest
@@ -348,7 +359,7 @@ def _make_fn():
             if g_dist is None or not (need_p or need_v):
                 return None, None, None
             gv = torch.zeros((len(mesh.V), 3), dtype=torch.float32, device=points.device) if need_v else None
-            gq, gv = query_backward(mesh, points, tri, g_dist, grad_points=need_p, grad_vertices=gv)
+            gq, gv = query_backward(mesh, points, tri, g_dist, grad_points=need_p, grad_vertices=gv, order=ctx.order)
             return gq, gv, None
 
     return _P2MDistance

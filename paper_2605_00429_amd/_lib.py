@@ -80,6 +80,7 @@ SIGNATURES = {
     "p2m_query": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP]),
     "p2m_point_set_distance": (_I32, [_VP, _VP, _I64, _VP, _VP]),
     "p2m_query_backward": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "p2m_query_backward_ordered": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP]),
     "p2m_query_fused": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "p2m_get_stats": (_I32, [_VP, ctypes.POINTER(p2m_stats)]),
     "p2m_get_query_config": (_I32, [_VP, ctypes.POINTER(p2m_query_config)]),
@@ -111,8 +112,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
-                              "(python -m paper_2605_00429_amd.build) first")
+            raise ImportError(f"{LIB_PATH} is missing: build it first "
+                              "(python -m paper_2605_00429_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

@@ -432,6 +432,23 @@ int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n, const
     return P2M_OK;
 }
 
+int32_t p2m_query_backward_ordered(p2m_handle h, const float* d_points, const int32_t* d_order, int64_t n,
+                                   const int32_t* d_tri, const float* d_grad_dist, float* d_grad_points,
+                                   float* d_grad_vertices, void* stream)
+{
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (n == 0) return P2M_OK;
+    if (!d_points || !d_tri || !d_grad_dist) return fail(P2M_ERR_INVALID_ARG, "null points, triangles or gradient");
+    if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
+    DeviceGuard dg(h->device);
+    hipError_t e = p2m::launch_backward(h->dm, d_points, n, d_order, d_tri, d_grad_dist, d_grad_points,
+                                        d_grad_vertices, h->cfg.block_size, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return P2M_OK;
+}
+
 // ------------------------------------------------------------ inspection
 
 int32_t p2m_host_sites(p2m_handle h, float* out_xyz, uint8_t* out_is_aux)

@@ -194,3 +194,25 @@ def test_autograd_matches_kernels(dev):
     torch.cuda.synchronize()
     assert torch.equal(q.grad, gq)
     assert rel_err(to_np(Vt.grad), to_np(gv)) <= 1e-5
+
+
+def test_backward_ordered_equals_backward(dev, c3):
+    """p2m_query_backward_ordered with the forward's visiting order (the
+    points sorted once) gives the same dL/dq and, up to the order of float32
+    additions, the same dL/dV as p2m_query_backward; so does the input order
+    (order None)."""
+    c, m = c3
+    q = torch.from_numpy(c["Q"][:500000]).cuda()
+    g = torch.from_numpy(c["G"][:500000]).cuda()
+    order = dev.sort_points(m, q)
+    d, t, cl = dev.query_ordered(m, q, order)
+    d0, t0, cl0 = dev.query(m, q)
+    assert torch.equal(d, d0) and torch.equal(t, t0)
+    gv0 = torch.zeros((len(m.V), 3), device="cuda")
+    gq0, gv0 = dev.query_backward(m, q, t, g, grad_vertices=gv0)
+    for o in (order, None):
+        gv1 = torch.zeros_like(gv0)
+        gq1, gv1 = dev.query_backward(m, q, t, g, grad_vertices=gv1, order=o)
+        torch.cuda.synchronize()
+        assert torch.equal(gq1, gq0)
+        assert rel_err(to_np(gv1), to_np(gv0)) <= 1e-5
