@@ -195,3 +195,22 @@ def test_c2_full_size_sampled(dev, c2):
     """Full C2 workload (10M points) in the benchmark's launch configuration."""
     c, m = c2
     print("C2 sample max|dd|/D, p99.9:", check_full_size(dev, c, m, 3000, 2024))
+
+
+def test_rejects_bad_counts_before_any_launch(dev):
+    """Point counts beyond 2^31 - 1 or negative are refused with
+    P2M_ERR_INVALID_ARG before any device memory is touched (the pointers
+    below are never read)."""
+    import ctypes
+    from paper_2605_00429_amd import _lib
+    V, F = gen.icosphere(2)
+    m = dev.Mesh(V, F)
+    buf = torch.empty(16, device="cuda")
+    p = ctypes.c_void_p(buf.data_ptr())
+    lib = dev.lib()
+    for n in (1 << 31, -1):
+        assert lib.p2m_query(m.handle, p, n, p, None, None, None) == _lib.P2M_ERR_INVALID_ARG
+        assert lib.p2m_point_set_distance(m.handle, p, n, p, None) == _lib.P2M_ERR_INVALID_ARG
+        assert lib.p2m_sort_points(m.handle, p, n, p, None, None) == _lib.P2M_ERR_INVALID_ARG
+        assert lib.p2m_query_backward(m.handle, p, n, p, None, None, p, None, None, None) == _lib.P2M_ERR_INVALID_ARG
+    assert lib.p2m_query(m.handle, p, 5, None, None, None, None) == _lib.P2M_ERR_INVALID_ARG   # null distance
