@@ -234,9 +234,6 @@ struct Best {
 // fetched kChunk at a time (all loads issued before any is used) so that
 // the scan keeps several requests in flight despite its data-dependent exit.
 constexpr int kChunk = 4;
-// Load whole entries with the chunk (one round trip per chunk) instead of
-// the second half only for entries that pass the sphere test.
-constexpr bool kFullRecord = false;
 
 // Scans at most `budget` entries; if the list is not done by then, *resume
 // is set to the next entry (else -1).
@@ -262,16 +259,12 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
         }
         // sphere (c, r) and (a, ell) of kChunk entries; the rest of an entry
         // (e1, e2) shares their cache line
-        float4 c[kChunk], a[kChunk], g2[kChunk], g3[kChunk];
+        float4 c[kChunk], a[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const int idx = min(e + k, rg.w - 1);
             c[k] = m.list_rec[4 * (int64_t)idx];
             a[k] = m.list_rec[4 * (int64_t)idx + 1];
-            if (kFullRecord) {
-                g2[k] = m.list_rec[4 * (int64_t)idx + 2];
-                g3[k] = m.list_rec[4 * (int64_t)idx + 3];
-            }
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
@@ -285,8 +278,7 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
             const float lim = dmin + c[k].w;
             if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) continue;
             const int64_t idx = e + k;
-            const float4 f2 = kFullRecord ? g2[k] : m.list_rec[4 * idx + 2];
-            const float4 f3 = kFullRecord ? g3[k] : m.list_rec[4 * idx + 3];
+            const float4 f2 = m.list_rec[4 * idx + 2], f3 = m.list_rec[4 * idx + 3];
             float v, w;
             const float d2 = closest_point(q, make_float3(a[k].x, a[k].y, a[k].z), make_float3(f2.x, f2.y, f2.z),
                                            make_float3(f3.x, f3.y, f3.z), f2.w, v, w);
@@ -762,8 +754,9 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
 }
 
 // ---------------------------------------------------------------- reorder
-// Counting sort by the Morton rank of the point's seed cell; points outside
-// the domain box or non-finite go to the last bucket.
+// Query sort: an LSD radix sort (8-bit digits) of the Morton code of each
+// point's cell in a 2^bits-per-axis grid over the seed-grid box; points
+// outside the domain box or non-finite get the largest code (last).
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n)
 {
