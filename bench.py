@@ -127,6 +127,9 @@ def bench_batched(args, plain_c2_mqps, stream):
     log(f"batched workload: {len(cfg)} meshes, {n_tris} triangles, {n} points; build {build_s:.1f}s")
     dev = torch.device("cuda", 0)
     q = torch.from_numpy(np.concatenate([c["Q"] for c in cfg], 0)).to(dev)
+    # a few meshes' points to check against the oracle afterwards
+    picks = sorted({0, len(cfg) // 2, len(cfg) - 1})
+    sample_src = [(cfg[i]["V"], cfg[i]["F"], cfg[i]["D"], i) for i in picks]
     del cfg
     g = torch.from_numpy(np.random.default_rng(2605_00429 + 4).normal(size=n).astype(np.float32)).to(dev)
     dist = torch.empty(n, device=dev)
@@ -196,9 +199,16 @@ def bench_batched(args, plain_c2_mqps, stream):
     }
     log(f"batched forward {ms_b:.3f} ms ({res['fwd_mqps']:.1f} Mq/s) vs {len(meshes)} plain calls "
         f"{ms_p:.3f} ms; fused batched {ms_bf:.3f} ms vs plain {ms_pf:.3f} ms")
+    b_fwd.launch(stream=stream)
+    torch.cuda.synchronize()
+    samples = []
+    for V, F, D, i in sample_src:
+        k = min(500, counts[i])
+        sl = slice(int(off[i]), int(off[i]) + k)
+        samples.append((V, F, D, q[sl].cpu().numpy(), dist[sl].cpu().numpy()))
     b_fwd.close()
     b_fus.close()
-    return res
+    return res, samples
 
 
 def bench_ablation(args, stream):
@@ -453,7 +463,7 @@ def main():
             log(f"{name}: {ms:.3f} ms/step = {result[f'{name}_mqps']:.1f} Mq/s")
 
     if not args.no_batched:
-        result["batched"] = bench_batched(args, mqps, stream)
+        result["batched"], batched_samples = bench_batched(args, mqps, stream)
 
     if args.octree:
         t0 = time.time()
@@ -494,6 +504,27 @@ def main():
         }
         result["max_abs_err_over_diag"] = float(err.max())
         log(f"oracle {cpu_s:.1f}s on {used} threads; GPU max |d - d64| / D = {err.max():.2e}")
+        # FP64 error of the other forms on the same samples (outside the timed regions)
+        fp64 = {"forward_max_abs_err_over_diag": float(err.max())}
+        if not args.no_grad:
+            t_gpu = out[1][torch.from_numpy(idx).to(dev)].cpu().numpy()
+            g_s = g[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
+            dq64, _ = oracle.gradient(V, F, Qs, t64, g_s)
+            gq_s = gq[torch.from_numpy(idx).to(dev)].cpu().numpy().astype(np.float64)
+            same = t_gpu == t64
+            rows = np.linalg.norm(gq_s - dq64, axis=1)[same]
+            scale = np.maximum(np.linalg.norm(dq64, axis=1)[same], 1e-3)
+            fp64["fused_grad_points_max_rel_err"] = float((rows / scale).max())
+            fp64["fused_grad_points_rows_compared"] = int(same.sum())
+        if not args.no_batched:
+            bmax = 0.0
+            for Vb, Fb, Db, Qb, db in batched_samples:
+                d64b, _, _, _ = oracle.distance(Vb, Fb, Qb, want_closest=False)
+                bmax = max(bmax, float(np.max(np.abs(db.astype(np.float64) - d64b)) / Db))
+            fp64["batched_max_abs_err_over_diag"] = bmax
+            fp64["batched_points_compared"] = int(sum(len(x[3]) for x in batched_samples))
+        result["fp64_error"] = fp64
+        log(f"FP64 error: {fp64}")
 
     print(json.dumps(result), flush=True)
 
