@@ -477,6 +477,42 @@ struct LdsAcc {
     }
 };
 
+// Adds each lane's dL/dV contributions (c: 3 values for each of the
+// triangle's 3 vertices) through acc, first summed over runs of consecutive
+// lanes on the same triangle (tri >= 0; -1 contributes nothing) by a
+// segmented suffix sum across the wavefront, so that only the first lane of
+// a run touches the accumulator: sorted points put neighbouring lanes on the
+// same triangle, and their atomics on one address would serialise.  Every
+// lane of the wavefront must call it.
+template <class Acc>
+__device__ __forceinline__ void add_vertex_grads(const DevMesh& m, const Acc& acc, const int tri, float c[9])
+{
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(tri, 1, 64);
+    const bool head = lane == 0 || tri < 0 || prev != tri;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1ull));
+    const int run = 63 - __builtin_clzll(upto);  // the run's first lane
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int r2 = __shfl_down(run, off, 64);
+        const bool same = lane + off < 64 && r2 == run;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const float o = __shfl_down(c[k], off, 64);
+            if (same) c[k] += o;
+        }
+    }
+    if (head && tri >= 0) {
+        const int4 vid = m.tri_vid[tri];
+        const int ids[3] = {vid.x, vid.y, vid.z};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (c[3 * k] != 0.f || c[3 * k + 1] != 0.f || c[3 * k + 2] != 0.f)
+                acc.add(ids[k], c[3 * k], c[3 * k + 1], c[3 * k + 2]);
+    }
+}
+
 // One query end to end: locate, list search (or fallback), outputs and,
 // when fused, the gradient.  Shared by the plain and the batched kernels so
 // that both give bitwise identical results.
@@ -519,12 +555,14 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
             exact += ex;
         }
     }
-    if (!valid) return;
-    if (finite && b.idx == -1) {
+    // the fused form's gradient step below is wavefront-wide: there every
+    // lane goes on
+    if (!kFused && !valid) return;
+    if (valid && finite && b.idx == -1) {
         b = bvh_search(m, q);
         fb = 1;
     }
-    if (kCtr) {
+    if (kCtr && valid) {
         atomicAdd(&ctr[CTR_WALK_STEPS], steps);
         atomicAdd(&ctr[CTR_ADJ_READ], adj_read);
         atomicAdd(&ctr[CTR_LIST_READ], list_read);
@@ -532,7 +570,9 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
         atomicAdd(&ctr[CTR_FALLBACK], fb);
         atomicAdd(&ctr[CTR_LIST_LEN], list_len);
     }
-    if (b.idx == -1) {
+    int gtri = -1;        // fused: this lane's triangle for dL/dV, or -1
+    float gc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (valid && b.idx == -1) {
         const float nan = __int_as_float(0x7fc00000);
         dist[i] = nan;
         if (tri) tri[i] = -1;
@@ -546,61 +586,62 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
             grad_q[3 * i + 1] = 0.f;
             grad_q[3 * i + 2] = 0.f;
         }
-        return;
-    }
-    // the winner's vertex a, edges e1, e2 and caller id: from its list entry
-    // (just scanned, so cache-resident), or from the triangle records
-    float4 r0, r1, r2;
-    int user;
-    if (b.idx >= 0) {
-        const float4* L = m.list_rec + 4 * (int64_t)b.idx;
-        r0 = L[1];
-        r1 = L[2];
-        r2 = L[3];
-        user = __float_as_int(r2.w);
-    } else {
-        const int slot = -b.idx - 2;
-        const float4* r = m.tri_rec + 3 * (int64_t)slot;
-        r0 = r[0];
-        r1 = r[1];
-        r2 = r[2];
-        user = m.tri_user[slot];
-    }
-    const float d = sqrtf(b.d2);
-    dist[i] = d;
-    if (tri) tri[i] = user;
-    if (closest) {
-        closest[3 * i] = r0.x + b.v * r1.x + b.w * r2.x;
-        closest[3 * i + 1] = r0.y + b.v * r1.y + b.w * r2.y;
-        closest[3 * i + 2] = r0.z + b.v * r1.z + b.w * r2.z;
-    }
-    if (kFused) {
-        const float g = gdist[i];
-        float nx = 0.f, ny = 0.f, nz = 0.f;
-        if (d > 0.f) {
-            // (q - p) / d from the same residual the distance came from
-            const float inv = 1.f / d;
-            nx = (q.x - r0.x - b.v * r1.x - b.w * r2.x) * inv;
-            ny = (q.y - r0.y - b.v * r1.y - b.w * r2.y) * inv;
-            nz = (q.z - r0.z - b.v * r1.z - b.w * r2.z) * inv;
+    } else if (valid) {
+        // the winner's vertex a, edges e1, e2 and caller id: from its list
+        // entry (just scanned, so cache-resident), or from the triangle records
+        float4 r0, r1, r2;
+        int user;
+        if (b.idx >= 0) {
+            const float4* L = m.list_rec + 4 * (int64_t)b.idx;
+            r0 = L[1];
+            r1 = L[2];
+            r2 = L[3];
+            user = __float_as_int(r2.w);
+        } else {
+            const int slot = -b.idx - 2;
+            const float4* r = m.tri_rec + 3 * (int64_t)slot;
+            r0 = r[0];
+            r1 = r[1];
+            r2 = r[2];
+            user = m.tri_user[slot];
         }
-        if (grad_q) {
-            grad_q[3 * i] = g * nx;
-            grad_q[3 * i + 1] = g * ny;
-            grad_q[3 * i + 2] = g * nz;
+        const float d = sqrtf(b.d2);
+        dist[i] = d;
+        if (tri) tri[i] = user;
+        if (closest) {
+            closest[3 * i] = r0.x + b.v * r1.x + b.w * r2.x;
+            closest[3 * i + 1] = r0.y + b.v * r1.y + b.w * r2.y;
+            closest[3 * i + 2] = r0.z + b.v * r1.z + b.w * r2.z;
         }
-        if (acc.gv && d > 0.f && g != 0.f) {
-            const int4 vid = m.tri_vid[user];
-            const float lam[3] = {1.f - b.v - b.w, b.v, b.w};
-            const int ids[3] = {vid.x, vid.y, vid.z};
+        if (kFused) {
+            const float g = gdist[i];
+            float nx = 0.f, ny = 0.f, nz = 0.f;
+            if (d > 0.f) {
+                // (q - p) / d from the same residual the distance came from
+                const float inv = 1.f / d;
+                nx = (q.x - r0.x - b.v * r1.x - b.w * r2.x) * inv;
+                ny = (q.y - r0.y - b.v * r1.y - b.w * r2.y) * inv;
+                nz = (q.z - r0.z - b.v * r1.z - b.w * r2.z) * inv;
+            }
+            if (grad_q) {
+                grad_q[3 * i] = g * nx;
+                grad_q[3 * i + 1] = g * ny;
+                grad_q[3 * i + 2] = g * nz;
+            }
+            if (d > 0.f && g != 0.f) {
+                const float lam[3] = {1.f - b.v - b.w, b.v, b.w};
+                gtri = user;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float s = -g * lam[k];
-                if (s == 0.f) continue;
-                acc.add(ids[k], s * nx, s * ny, s * nz);
+                for (int k = 0; k < 3; ++k) {
+                    const float s = -g * lam[k];
+                    gc[3 * k] = s * nx;
+                    gc[3 * k + 1] = s * ny;
+                    gc[3 * k + 2] = s * nz;
+                }
             }
         }
     }
+    if (kFused && acc.gv) add_vertex_grads(m, acc, gtri, gc);
 }
 
 // Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
@@ -714,6 +755,8 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
     if (grad_v) acc.init();
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int gtri = -1;
+    float gc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (j < n) {
         const int64_t i = order ? (int64_t)order[j] : j;
         const int t = tri[i];
@@ -737,18 +780,19 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
             grad_q[3 * i + 1] = g * ny;
             grad_q[3 * i + 2] = g * nz;
         }
-        if (grad_v && d > 0.f && g != 0.f) {
-            const int4 vid = m.tri_vid[t];
+        if (d > 0.f && g != 0.f) {
             const float lam[3] = {1.f - v - w, v, w};
-            const int ids[3] = {vid.x, vid.y, vid.z};
+            gtri = t;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const float s = -g * lam[k];
-                if (s == 0.f) continue;
-                acc.add(ids[k], s * nx, s * ny, s * nz);
+                gc[3 * k] = s * nx;
+                gc[3 * k + 1] = s * ny;
+                gc[3 * k + 2] = s * nz;
             }
         }
     }
+    if (grad_v) add_vertex_grads(m, acc, gtri, gc);
     __syncthreads();
     if (grad_v) acc.flush();
 }
