@@ -440,8 +440,9 @@ struct DirectAcc {
 struct LdsAcc {
     float* gv;
     int* keys;
-    float* val;   // 3 per slot
-    int slots;    // power of two
+    float* val;         // 3 per slot
+    int slots;          // power of two
+    int* used = nullptr;  // if set, counts the slots taken
     static constexpr int kProbe = 32;
 
     __device__ __forceinline__ void init() const
@@ -459,6 +460,7 @@ struct LdsAcc {
         for (int p = 0; p < kProbe; ++p) {
             const int slot = (int)((h + (uint32_t)p) & (uint32_t)(slots - 1));
             const int prev = atomicCAS(&keys[slot], -1, vid);
+            if (prev == -1 && used) atomicAdd(used, 1);
             if (prev == -1 || prev == vid) {
                 atomicAdd(&val[3 * slot], x);
                 atomicAdd(&val[3 * slot + 1], y);
@@ -473,6 +475,20 @@ struct LdsAcc {
         for (int s = threadIdx.x; s < slots; s += blockDim.x) {
             const int k = keys[s];
             if (k >= 0) DirectAcc{gv}.add(k, val[3 * s], val[3 * s + 1], val[3 * s + 2]);
+        }
+    }
+    // flush, and leave the table empty
+    __device__ __forceinline__ void flush_clear() const
+    {
+        for (int s = threadIdx.x; s < slots; s += blockDim.x) {
+            const int k = keys[s];
+            if (k >= 0) {
+                DirectAcc{gv}.add(k, val[3 * s], val[3 * s + 1], val[3 * s + 2]);
+                keys[s] = -1;
+                val[3 * s] = 0.f;
+                val[3 * s + 1] = 0.f;
+                val[3 * s + 2] = 0.f;
+            }
         }
     }
 };
@@ -666,16 +682,22 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
                                DirectAcc{nullptr}, a.ctr);
         return;
     }
-    // fused: vertex gradients combined per workgroup in LDS (every thread
-    // reaches both barriers)
+    // fused: vertex gradients combined per workgroup in an LDS table,
+    // flushed once all its wavefronts are done (every thread reaches both
+    // barriers); without dL/dV there is no table and no barrier
     extern __shared__ int acc_smem[];
     const LdsAcc acc{a.grad_v, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
-    if (a.grad_v) acc.init();
+    if (!a.grad_v) {
+        run_query<true, kCtr>(m, valid, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist,
+                              a.grad_q, acc, a.ctr);
+        return;
+    }
+    acc.init();
     __syncthreads();
     run_query<true, kCtr>(m, valid, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q,
                           acc, a.ctr);
     __syncthreads();
-    if (a.grad_v) acc.flush();
+    acc.flush();
 }
 
 // Persistent batched kernel: each wavefront takes work items (up to `tile`
@@ -748,52 +770,74 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
                                                    const int32_t* __restrict__ order,
                                                    const int32_t* __restrict__ tri, const float* __restrict__ gd,
                                                    float* __restrict__ grad_q, float* __restrict__ grad_v,
-                                                   int acc_slots)
+                                                   int acc_slots, int tiles)
 {
+    // One workgroup takes `tiles` consecutive tiles of blockDim points in
+    // visiting order and keeps one LDS table of vertex gradients across
+    // them (the slots' keys and values, then the count of slots taken).  It
+    // is flushed to dL/dV once more than half of it is taken, and at the
+    // end: consecutive tiles of sorted points share most of their vertices,
+    // so a vertex reaches global memory once per run of tiles, not per tile.
     extern __shared__ int acc_smem[];
-    const LdsAcc acc{grad_v, acc_smem, (float*)(acc_smem + acc_slots), acc_slots};
-    if (grad_v) acc.init();
+    int* used = acc_smem + 4 * acc_slots;
+    const LdsAcc acc{grad_v, acc_smem, (float*)(acc_smem + acc_slots), acc_slots, used};
+    if (grad_v) {
+        acc.init();
+        if (threadIdx.x == 0) *used = 0;
+    }
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int gtri = -1;
-    float gc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (j < n) {
-        const int64_t i = order ? (int64_t)order[j] : j;
-        const int t = tri[i];
-        float nx = 0.f, ny = 0.f, nz = 0.f, g = 0.f, v = 0.f, w = 0.f, d = 0.f;
-        if (t >= 0 && t < m.n_tris) {
-            const int slot = m.tri_slot[t];
-            const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
-            const float4* r = m.tri_rec + 3 * (int64_t)slot;
-            const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-            d = sqrtf(closest_point_rec(q, r, v, w));
-            g = gd[i];
-            if (d > 0.f) {
-                const float inv = 1.f / d;
-                nx = (q.x - r0.x - v * r1.x - w * r2.x) * inv;
-                ny = (q.y - r0.y - v * r1.y - w * r2.y) * inv;
-                nz = (q.z - r0.z - v * r1.z - w * r2.z) * inv;
+    for (int t = 0; t < tiles; ++t) {
+        const int64_t j = ((int64_t)blockIdx.x * tiles + t) * blockDim.x + threadIdx.x;
+        int gtri = -1;
+        float gc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (j < n) {
+            const int64_t i = order ? (int64_t)order[j] : j;
+            const int tt = tri[i];
+            float nx = 0.f, ny = 0.f, nz = 0.f, g = 0.f, v = 0.f, w = 0.f, d = 0.f;
+            if (tt >= 0 && tt < m.n_tris) {
+                const int slot = m.tri_slot[tt];
+                const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
+                const float4* r = m.tri_rec + 3 * (int64_t)slot;
+                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+                d = sqrtf(closest_point_rec(q, r, v, w));
+                g = gd[i];
+                if (d > 0.f) {
+                    const float inv = 1.f / d;
+                    nx = (q.x - r0.x - v * r1.x - w * r2.x) * inv;
+                    ny = (q.y - r0.y - v * r1.y - w * r2.y) * inv;
+                    nz = (q.z - r0.z - v * r1.z - w * r2.z) * inv;
+                }
             }
-        }
-        if (grad_q) {
-            grad_q[3 * i] = g * nx;
-            grad_q[3 * i + 1] = g * ny;
-            grad_q[3 * i + 2] = g * nz;
-        }
-        if (d > 0.f && g != 0.f) {
-            const float lam[3] = {1.f - v - w, v, w};
-            gtri = t;
+            if (grad_q) {
+                grad_q[3 * i] = g * nx;
+                grad_q[3 * i + 1] = g * ny;
+                grad_q[3 * i + 2] = g * nz;
+            }
+            if (d > 0.f && g != 0.f) {
+                const float lam[3] = {1.f - v - w, v, w};
+                gtri = tt;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float s = -g * lam[k];
-                gc[3 * k] = s * nx;
-                gc[3 * k + 1] = s * ny;
-                gc[3 * k + 2] = s * nz;
+                for (int k = 0; k < 3; ++k) {
+                    const float s = -g * lam[k];
+                    gc[3 * k] = s * nx;
+                    gc[3 * k + 1] = s * ny;
+                    gc[3 * k + 2] = s * nz;
+                }
             }
+        }
+        if (!grad_v) continue;
+        add_vertex_grads(m, acc, gtri, gc);
+        // every thread reads the count between two barriers, so that all
+        // take the same branch
+        __syncthreads();
+        const int u = *used;
+        __syncthreads();
+        if (u > acc_slots / 2 && t + 1 < tiles) {
+            acc.flush_clear();
+            if (threadIdx.x == 0) *used = 0;
+            __syncthreads();
         }
     }
-    if (grad_v) add_vertex_grads(m, acc, gtri, gc);
-    __syncthreads();
     if (grad_v) acc.flush();
 }
 
@@ -864,11 +908,16 @@ __global__ void __launch_bounds__(kSortBlock) radix_upsweep(const DevMesh m, con
     counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = hist[threadIdx.x];
 }
 
-// Downsweep: the tile is ranked stably by digit into LDS (per 256-key
-// round: ballots give the rank among a wavefront's lanes with the same
-// digit, per-wavefront counts order the wavefronts), then written out in
-// that order, so that consecutive threads write consecutive addresses of a
-// digit's run instead of scattering one element per digit per round.
+// Downsweep: the tile is ranked stably by digit into LDS, then written out
+// in that order, so that consecutive threads write consecutive addresses of
+// a digit's run instead of scattering one element per digit.  Wavefront w
+// holds the tile's w-th quarter.  It ranks its keys by itself, 64 at a time
+// (ballots over the digit bits find the lanes with the same digit, a
+// running count per digit in the wavefront's own LDS row orders the
+// rounds), so that only the combination of the four rows into each
+// wavefront's start per digit needs the workgroup's barriers.  Tile order
+// is (wavefront, round, lane) order, so the sort stays stable.  keys_out
+// may be null (last pass: only the values are needed).
 template <bool kFromPoints>
 __global__ void __launch_bounds__(kSortBlock) radix_downsweep(
     const DevMesh m, const float* __restrict__ qp, const uint32_t* __restrict__ keys_in,
@@ -876,56 +925,40 @@ __global__ void __launch_bounds__(kSortBlock) radix_downsweep(
     const uint32_t* __restrict__ offsets, int64_t n_tiles, uint32_t* __restrict__ keys_out,
     int32_t* __restrict__ vals_out, float* __restrict__ sorted_q)
 {
+    constexpr int kWaves = kSortBlock / 64;
+    constexpr int kPerWave = kSortTile / kWaves;
+    static_assert(kPerWave == 64 * kSortIters, "a wavefront ranks kSortIters rounds of 64 keys");
     __shared__ uint32_t lkey[kSortTile];
     __shared__ int32_t lval[kSortTile];
-    __shared__ uint32_t run[256], lstart[256], gbase[256];
-    __shared__ uint32_t wcnt[kSortBlock / 64][256];
+    __shared__ uint32_t wc[kWaves][256];  // per-wavefront digit counts, then starts
+    __shared__ uint32_t lstart[256], gbase[256], wsum[kWaves];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    run[tid] = 0u;
+    const int64_t wbase = base + (int64_t)wid * kPerWave;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wc[w][tid] = 0u;
     gbase[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
-    __syncthreads();
     uint32_t key[kSortIters];
     int32_t val[kSortIters];
 #pragma unroll
     for (int it = 0; it < kSortIters; ++it) {
-        const int64_t idx = base + it * kSortBlock + tid;
+        const int64_t idx = wbase + it * 64 + lane;
         key[it] = 0u;
         val[it] = 0;
         if (idx < n) {
             key[it] = kFromPoints ? point_key(m, qp, idx, bits, sx, sy, sz) : keys_in[idx];
             val[it] = kFromPoints ? (int32_t)idx : vals_in[idx];
-            atomicAdd(&run[(key[it] >> shift) & 255u], 1u);
         }
     }
     __syncthreads();
-    // exclusive scan of the tile's digit counts: the local start of each digit
-    if (wid == 0) {
-        const uint32_t v0 = run[4 * lane], v1 = run[4 * lane + 1], v2 = run[4 * lane + 2], v3 = run[4 * lane + 3];
-        const uint32_t t = v0 + v1 + v2 + v3;
-        uint32_t inc = t;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(inc, off, 64);
-            if (lane >= off) inc += y;
-        }
-        const uint32_t ex = inc - t;
-        lstart[4 * lane] = ex;
-        lstart[4 * lane + 1] = ex + v0;
-        lstart[4 * lane + 2] = ex + v0 + v1;
-        lstart[4 * lane + 3] = ex + v0 + v1 + v2;
-    }
-    __syncthreads();
-    run[tid] = lstart[tid];
+    // rank within the wavefront: wrank = earlier keys of this wavefront with
+    // the same digit
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t wrank[kSortIters];
 #pragma unroll
     for (int it = 0; it < kSortIters; ++it) {
-#pragma unroll
-        for (int w = 0; w < kSortBlock / 64; ++w) wcnt[w][tid] = 0u;
-        __syncthreads();
-        const bool valid = base + it * kSortBlock + tid < n;
+        const bool valid = wbase + it * 64 + lane < n;
         const uint32_t d = (key[it] >> shift) & 255u;
-        // lanes of this wavefront holding the same digit
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -933,20 +966,49 @@ __global__ void __launch_bounds__(kSortBlock) radix_downsweep(
             const uint64_t m1 = __ballot(bit);
             peers &= bit ? m1 : ~m1;
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & below);
-        if (valid && rank == 0u) wcnt[wid][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[d] + rank;
-            for (int w = 0; w < wid; ++w) pos += wcnt[w][d];
+        const int leader = valid ? __builtin_ctzll(peers) : lane;
+        uint32_t prev = 0u;
+        // one leader per digit: this wavefront's row, distinct addresses
+        if (valid && lane == leader) {
+            prev = wc[wid][d];
+            wc[wid][d] = prev + (uint32_t)__popcll(peers);
+        }
+        prev = (uint32_t)__shfl((int)prev, leader, 64);
+        wrank[it] = prev + (uint32_t)__popcll(peers & below);
+    }
+    __syncthreads();
+    // thread tid = digit: the tile's exclusive start per digit, then each
+    // wavefront's start within it
+    uint32_t c[kWaves], tot = 0u;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        c[w] = wc[w][tid];
+        tot += c[w];
+    }
+    uint32_t inc = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t start = inc - tot;
+    for (int w = 0; w < wid; ++w) start += wsum[w];
+    lstart[tid] = start;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        wc[w][tid] = start;
+        start += c[w];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kSortIters; ++it) {
+        if (wbase + it * 64 + lane < n) {
+            const uint32_t pos = wc[wid][(key[it] >> shift) & 255u] + wrank[it];
             lkey[pos] = key[it];
             lval[pos] = val[it];
         }
-        __syncthreads();
-        uint32_t add = 0u;
-#pragma unroll
-        for (int w = 0; w < kSortBlock / 64; ++w) add += wcnt[w][tid];
-        run[tid] += add;
     }
     __syncthreads();
     const int cnt = (int)min((int64_t)kSortTile, n - base);
@@ -955,7 +1017,7 @@ __global__ void __launch_bounds__(kSortBlock) radix_downsweep(
         const int32_t v = lval[j];
         const uint32_t d = (k >> shift) & 255u;
         const uint32_t pos = gbase[d] + ((uint32_t)j - lstart[d]);
-        keys_out[pos] = k;
+        if (keys_out) keys_out[pos] = k;
         vals_out[pos] = v;
         if (sorted_q) {
             sorted_q[3 * (int64_t)pos] = qp[3 * (int64_t)v];
@@ -1030,6 +1092,20 @@ inline int acc_slots_for(int block)
 
 inline size_t acc_lds_bytes(int slots) { return (size_t)slots * 16; }
 
+// Slots of an LDS table plus its 16-byte count within 64 KB of LDS.
+inline int acc_slots_capped(int want)
+{
+    int s = 1;
+    while (s < want) s <<= 1;
+    while (s > 64 && acc_lds_bytes(s) + 16 > 65536) s >>= 1;
+    return s;
+}
+
+// Backward: LDS table slots per thread of the workgroup, and the number of
+// rounds of resident workgroups the grid is sized for.
+constexpr int kBwdSlotsPerThread = 4;
+constexpr int kBwdRounds = 4;
+
 // Exclusive scan of n uint32 in place; tmp holds scan_levels scratch.
 hipError_t exclusive_scan(uint32_t* data, int64_t n, uint32_t* tmp, hipStream_t st)
 {
@@ -1067,7 +1143,7 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
     args.xcds = x;
     if (fused) {
         args.acc_slots = acc_slots_for(block);
-        const size_t lds = acc_lds_bytes(args.acc_slots);
+        const size_t lds = a.grad_v ? acc_lds_bytes(args.acc_slots) : 0;
         if (counters) fwd_kernel<true, true><<<g, block, lds, st>>>(m, args);
         else fwd_kernel<true, false><<<g, block, lds, st>>>(m, args);
     } else {
@@ -1082,9 +1158,24 @@ hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const in
                            hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    const int slots = acc_slots_for(block);
-    bwd_kernel<<<grid_for(n, block), block, acc_lds_bytes(slots), st>>>(m, q, n, order, tri, g, grad_q, grad_v,
-                                                                         slots);
+    const int slots = acc_slots_capped(kBwdSlotsPerThread * block);
+    const size_t lds = grad_v ? acc_lds_bytes(slots) + 16 : 0;
+    const int64_t n_tiles = (n + block - 1) / block;
+    // with dL/dV, as few workgroups as fill the GPU kBwdRounds times, each
+    // over consecutive tiles (fewer flushes of the table)
+    int64_t tiles = 1;
+    if (grad_v) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bwd_kernel, block, lds) == hipSuccess && cus > 0 &&
+            per_cu > 0) {
+            const int64_t slots_total = (int64_t)kBwdRounds * cus * per_cu;
+            tiles = std::min<int64_t>(64, (n_tiles + slots_total - 1) / slots_total);
+        }
+    }
+    const int64_t grid = (n_tiles + tiles - 1) / tiles;
+    bwd_kernel<<<(unsigned)grid, block, lds, st>>>(m, q, n, order, tri, g, grad_q, grad_v, slots, (int)tiles);
     return hipGetLastError();
 }
 
@@ -1136,7 +1227,9 @@ hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, int bits,
     uint32_t *kin = nullptr, *kout = ka;
     int32_t *vin = nullptr, *vout = va;
     for (int shift = 0; shift < key_bits; shift += 8) {
-        float* sq = (shift + 8 >= key_bits) ? sorted_q : nullptr;  // last pass
+        const bool last = shift + 8 >= key_bits;
+        float* sq = last ? sorted_q : nullptr;
+        uint32_t* ko = last ? nullptr : kout;
         if (shift == 0) {
             radix_upsweep<true><<<grid, kSortBlock, 0, st>>>(m, q, nullptr, n, shift, bits, sx, sy, sz, counts, n_tiles);
         } else {
@@ -1146,10 +1239,10 @@ hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, int bits,
         if (e != hipSuccess) return e;
         if (shift == 0) {
             radix_downsweep<true><<<grid, kSortBlock, 0, st>>>(m, q, nullptr, nullptr, n, shift, bits, sx, sy, sz,
-                                                               counts, n_tiles, kout, vout, sq);
+                                                               counts, n_tiles, ko, vout, sq);
         } else {
             radix_downsweep<false><<<grid, kSortBlock, 0, st>>>(m, q, kin, vin, n, shift, bits, sx, sy, sz, counts,
-                                                                n_tiles, kout, vout, sq);
+                                                                n_tiles, ko, vout, sq);
         }
         kin = kout;
         vin = vout;

@@ -88,6 +88,11 @@ def test_c3_full_size_invariants_and_fused(dev, c3):
     assert torch.equal(d, d2) and torch.equal(t, t2) and torch.equal(cl, cl2)
     assert torch.equal(gq, gq2)
     assert rel_err(to_np(gv2), to_np(gv)) <= 1e-5          # atomics order only
+    # without dL/dV (no LDS table, no barrier): the same outputs and dL/dq
+    d3, t3, cl3, gq3 = dev.query_fused(m, q, g)
+    torch.cuda.synchronize()
+    assert torch.equal(d, d3) and torch.equal(t, t3) and torch.equal(cl, cl3)
+    assert torch.equal(gq, gq3)
     dn, gqn, gn = to_np(d), to_np(gq), np.abs(c["G"])
     pos = dn > 1e-6
     assert np.allclose(np.linalg.norm(gqn[pos], axis=1), gn[pos], rtol=1e-5, atol=1e-6)   # |dd/dq| = 1
@@ -216,3 +221,28 @@ def test_backward_ordered_equals_backward(dev, c3):
         torch.cuda.synchronize()
         assert torch.equal(gq1, gq0)
         assert rel_err(to_np(gv1), to_np(gv0)) <= 1e-5
+
+
+def test_backward_table_flushes(dev, c3):
+    """At 4M points a backward workgroup runs over several tiles with one LDS
+    table of vertex gradients.  In input order (random in space) the table
+    fills within a tile or two and is flushed and cleared between tiles;
+    sorted, it is flushed at the end.  Both give the same dL/dV up to the
+    order of float32 additions, and dL/dq bit for bit."""
+    c, m = c3
+    q = torch.from_numpy(c["Q"]).cuda()
+    g = torch.from_numpy(c["G"]).cuda()
+    order = dev.sort_points(m, q)
+    d, t, cl = dev.query_ordered(m, q, order)
+    ident = torch.arange(len(q), dtype=torch.int32, device="cuda")
+    gv0 = torch.zeros((len(m.V), 3), device="cuda")
+    gq0, gv0 = dev.query_backward(m, q, t, g, grad_vertices=gv0, order=order)
+    gv1 = torch.zeros_like(gv0)
+    gq1, gv1 = dev.query_backward(m, q, t, g, grad_vertices=gv1, order=ident)
+    torch.cuda.synchronize()
+    assert torch.equal(gq1, gq0)
+    assert rel_err(to_np(gv1), to_np(gv0)) <= 1e-5
+    # translating mesh and points together leaves d unchanged
+    for gv in (gv0, gv1):
+        s = to_np(gq0).astype(np.float64).sum(0) + to_np(gv).astype(np.float64).sum(0)
+        assert np.linalg.norm(s) <= 1e-4 * np.abs(to_np(gq0)).sum()
