@@ -67,10 +67,11 @@ def bytes_per_query(ctr, n):
 def layout_bytes_per_query(ctr, n):
     """Bytes the kernel's own layout reads per query (each touch counted
     once): point 12, order 4, seed 4, per visited site 32, adjacency entries
-    16, located site 32, 32 per scanned list entry (sphere, first vertex and
-    ell), 32 more per exact test, the winner's record 48 + id 4, outputs 20."""
+    16, located site 32, 16 per scanned list entry (its sphere), 48 more per
+    exact test (first vertex and both edges), the winner's record 48 + id 4,
+    outputs 20."""
     return (12 + 4 + 4 + 32 * ctr["walk_steps"] / n + 16 * ctr["adj_read"] / n + 32
-            + 32 * ctr["list_read"] / n + 32 * ctr["exact_tests"] / n + 52 + 20)
+            + 16 * ctr["list_read"] / n + 48 * ctr["exact_tests"] / n + 52 + 20)
 
 
 # Backward per query: q 12, tri 4, closest 12, dist 4, g 4, vertex ids 12,

@@ -11,7 +11,8 @@ namespace p2m {
 struct DevMesh {
     const float4* site_rec;  // 2 per site: (x, y, z, 0), int4 (adj begin, end, list begin, end)
     const float4* adj;       // neighbour xyz + id bits
-    const float4* list_rec;  // 4 per list entry: (c, r), (a, ell), (e1, e1.e2), (e2, caller triangle id bits)
+    const float4* list_rec;  // 4 per list entry: (c, r), (a, ell), (e1, e1.e2), (e2, caller triangle id bits);
+                             // the scan recomputes a lower bound of ell from (c, r)
     const float4* tri_rec;   // 3 per slot: (a, |e1|^2), (e1, e1.e2), (e2, |e2|^2)
     const int32_t* tri_user; // slot -> caller triangle id
     const int4* tri_vid;     // caller triangle id -> caller vertex ids

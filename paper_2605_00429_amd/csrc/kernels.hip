@@ -257,20 +257,30 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
             stop = e;
             break;
         }
-        // sphere (c, r) and (a, ell) of kChunk entries; the rest of an entry
-        // (e1, e2) shares their cache line
-        float4 c[kChunk], a[kChunk];
+        // the spheres (c, r) of kChunk entries; the rest of an entry (a, e1,
+        // e2) shares their cache line and is read for an exact test only
+        float4 c[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const int idx = min(e + k, rg.w - 1);
             c[k] = m.list_rec[4 * (int64_t)idx];
-            a[k] = m.list_rec[4 * (int64_t)idx + 1];
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             if (e + k >= stop) break;
-            // sorted by ell: no later entry can beat d_min (triangle inequality)
-            if (a[k].w - dqs >= dmin) {
+            // Sorted by ell = |s - c| - r: no later entry can beat d_min
+            // (triangle inequality).  ell is recomputed from (c, r) rather
+            // than loaded, which keeps the scan to one 16-byte load per
+            // entry.  The two terms are pulled apart by 1e-6 relative, more
+            // than the float32 rounding of the differences, the sum of
+            // squares, the square root and the subtraction together, so the
+            // value never exceeds the exact ell of the same float32 values
+            // by which the lists were sorted.  (Written out here: as a
+            // helper function the compiler waited for each chunk's first
+            // load before issuing the others.)
+            const float ux = sp.x - c[k].x, uy = sp.y - c[k].y, uz = sp.z - c[k].z;
+            const float ell = sqrtf(ux * ux + uy * uy + uz * uz) * (1.f - 1e-6f) - c[k].w * (1.f + 1e-6f);
+            if (ell - dqs >= dmin) {
                 stop = e + k;
                 break;
             }
@@ -278,9 +288,9 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
             const float lim = dmin + c[k].w;
             if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) continue;
             const int64_t idx = e + k;
-            const float4 f2 = m.list_rec[4 * idx + 2], f3 = m.list_rec[4 * idx + 3];
+            const float4 f1 = m.list_rec[4 * idx + 1], f2 = m.list_rec[4 * idx + 2], f3 = m.list_rec[4 * idx + 3];
             float v, w;
-            const float d2 = closest_point(q, make_float3(a[k].x, a[k].y, a[k].z), make_float3(f2.x, f2.y, f2.z),
+            const float d2 = closest_point(q, make_float3(f1.x, f1.y, f1.z), make_float3(f2.x, f2.y, f2.z),
                                            make_float3(f3.x, f3.y, f3.z), f2.w, v, w);
             if (kCtr) exact += 1;
             if (d2 < b.d2) {
