@@ -161,12 +161,14 @@ __device__ __noinline__ int best_neighbour_f64(const DevMesh& m, const float3 q,
 // would (a local, hence global, minimum on the Delaunay graph).
 template <bool kCtr>
 __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned long long& steps,
-                                      unsigned long long& adj_read)
+                                      unsigned long long& adj_read, float4& sp_out, int4& rg_out)
 {
     int s = m.seed[seed_cell(m, q)];
     for (int it = 0; it < kWalkCap; ++it) {
         const float4 sp = m.site_rec[2 * s];
         const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        sp_out = sp;
+        rg_out = rg;
         const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
         const float wn = fabsf(wx) + fabsf(wy) + fabsf(wz);
         float best = 0.f;
@@ -196,9 +198,12 @@ __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned
             adj_read += (unsigned long long)(rg.y - rg.x);
         }
         if (nxt < 0 && unsure) nxt = best_neighbour_f64(m, q, sp, rg);
-        if (nxt < 0) break;
+        if (nxt < 0) return s;
         s = nxt;
     }
+    // walk cap reached (not on a valid Delaunay graph): s's record
+    sp_out = m.site_rec[2 * s];
+    rg_out = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
     return s;
 }
 
@@ -235,15 +240,14 @@ struct Best {
 // the scan keeps several requests in flight despite its data-dependent exit.
 constexpr int kChunk = 4;
 
-// Scans at most `budget` entries; if the list is not done by then, *resume
-// is set to the next entry (else -1).
+// Scans at most `budget` entries of the list of the site whose record is
+// (sp, rg); if the list is not done by then, *resume is set to the next
+// entry (else -1).
 template <bool kCtr>
-__device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, const int s, const int budget,
-                                            int* resume, unsigned long long& list_read,
+__device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, const float4 sp, const int4 rg,
+                                            const int budget, int* resume, unsigned long long& list_read,
                                             unsigned long long& exact, unsigned long long& list_len)
 {
-    const float4 sp = m.site_rec[2 * s];
-    const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
     const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
     // |q - s| rounded up so that the early-exit bound stays conservative
     const float dqs = sqrtf(wx * wx + wy * wy + wz * wz) * 1.000001f;
@@ -560,8 +564,18 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
     const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
     int s = -1, resume = -1;
     if (finite && in_domain(m, q)) {
-        s = m.oct ? octree_locate(m, q, steps) : locate<kCtr>(m, q, steps, adj_read);
-        b = list_search<kCtr>(m, q, s, kSerialBudget, &resume, list_read, exact, list_len);
+        // the site's record (position, adjacency and list ranges): the walk
+        // has just read it
+        float4 sp;
+        int4 rg;
+        if (m.oct) {
+            s = octree_locate(m, q, steps);
+            sp = m.site_rec[2 * s];
+            rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        } else {
+            s = locate<kCtr>(m, q, steps, adj_read, sp, rg);
+        }
+        b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, list_read, exact, list_len);
     }
     // lists not done within the budget: finished by the whole wavefront
     for (uint64_t todo = __ballot(resume >= 0); todo; todo &= todo - 1) {
