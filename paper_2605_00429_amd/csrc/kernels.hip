@@ -543,40 +543,30 @@ __device__ __forceinline__ void add_vertex_grads(const DevMesh& m, const Acc& ac
     }
 }
 
-// One query end to end: locate, list search (or fallback), outputs and,
-// when fused, the gradient.  Shared by the plain and the batched kernels so
-// that both give bitwise identical results.
+// Counts of one query for the instrumented forward.
+struct QueryCounts {
+    unsigned long long steps = 0, adj_read = 0, list_read = 0, exact = 0, list_len = 0;
+};
+
+// The rest of one query after its lane's part of the list scan: lists left
+// unfinished (resume >= 0) are completed by the wavefront, then fallback,
+// outputs and, when fused, the gradient.  q is the point (finite tells
+// whether all its coordinates are), s its located site or -1 when q is not
+// finite or outside the domain box, b the scan's best so far; i is the
+// output position.
 //
 // Every lane of the wavefront must call it (valid = false for a lane without
 // a query): long lists are scanned by the whole wavefront.
 template <bool kFused, bool kCtr, class Acc>
-__device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, const int64_t iq, const int64_t i,
-                                          const float* __restrict__ qp, float* __restrict__ dist,
-                                          int32_t* __restrict__ tri, float* __restrict__ closest,
-                                          const float* __restrict__ gdist, float* __restrict__ grad_q,
-                                          const Acc& acc, unsigned long long* __restrict__ ctr)
+__device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid, const float3 q, const bool finite,
+                                             const int s, Best b, const int resume, const int64_t i,
+                                             float* __restrict__ dist, int32_t* __restrict__ tri,
+                                             float* __restrict__ closest, const float* __restrict__ gdist,
+                                             float* __restrict__ grad_q, const Acc& acc,
+                                             unsigned long long* __restrict__ ctr, QueryCounts n)
 {
-    // the point is read at iq (its slot in qp), every output and gradient at i
-    float3 q = make_float3(0.f, 0.f, 0.f);
-    if (valid) q = make_float3(qp[3 * iq], qp[3 * iq + 1], qp[3 * iq + 2]);
-    unsigned long long steps = 0, adj_read = 0, list_read = 0, exact = 0, list_len = 0, fb = 0;
-    Best b{kInf, -1, 0.f, 0.f};
-    const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
-    int s = -1, resume = -1;
-    if (finite && in_domain(m, q)) {
-        // the site's record (position, adjacency and list ranges): the walk
-        // has just read it
-        float4 sp;
-        int4 rg;
-        if (m.oct) {
-            s = octree_locate(m, q, steps);
-            sp = m.site_rec[2 * s];
-            rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
-        } else {
-            s = locate<kCtr>(m, q, steps, adj_read, sp, rg);
-        }
-        b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, list_read, exact, list_len);
-    }
+    unsigned long long steps = n.steps, adj_read = n.adj_read, list_read = n.list_read, exact = n.exact,
+                       list_len = n.list_len, fb = 0;
     // lists not done within the budget: finished by the whole wavefront
     for (uint64_t todo = __ballot(resume >= 0); todo; todo &= todo - 1) {
         const int src = __builtin_ctzll(todo);
@@ -684,6 +674,112 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
     if (kFused && acc.gv) add_vertex_grads(m, acc, gtri, gc);
 }
 
+// One query end to end: the point read at iq (its slot in qp), located by
+// the walk (or the octree descent), then finish_query with outputs at i.
+// Shared by the fused and the batched kernels.  Every lane of the wavefront
+// must call it.
+template <bool kFused, bool kCtr, class Acc>
+__device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, const int64_t iq, const int64_t i,
+                                          const float* __restrict__ qp, float* __restrict__ dist,
+                                          int32_t* __restrict__ tri, float* __restrict__ closest,
+                                          const float* __restrict__ gdist, float* __restrict__ grad_q,
+                                          const Acc& acc, unsigned long long* __restrict__ ctr)
+{
+    float3 q = make_float3(0.f, 0.f, 0.f);
+    if (valid) q = make_float3(qp[3 * iq], qp[3 * iq + 1], qp[3 * iq + 2]);
+    const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
+    QueryCounts n;
+    Best b{kInf, -1, 0.f, 0.f};
+    int s = -1, resume = -1;
+    if (finite && in_domain(m, q)) {
+        // the site's record (position, adjacency and list ranges): the walk
+        // has just read it
+        float4 sp;
+        int4 rg;
+        if (m.oct) {
+            s = octree_locate(m, q, n.steps);
+            sp = m.site_rec[2 * s];
+            rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        } else {
+            s = locate<kCtr>(m, q, n.steps, n.adj_read, sp, rg);
+        }
+        b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n.list_read, n.exact, n.list_len);
+    }
+    finish_query<kFused, kCtr>(m, valid, q, finite, s, b, resume, i, dist, tri, closest, gdist, grad_q, acc, ctr,
+                               n);
+}
+
+// Regroups a workgroup's queries by located site, so that lanes holding
+// the same site become neighbours: the list scans of a wavefront then read
+// the same entries, one cache line serving many lanes, instead of a few
+// dozen sites' lists at once.  Each lane passes its query (q, output
+// position i or -1 for none, site s or -1) and gets back the one it is to
+// finish.  The key is the site's low 8 bits (queries without a site take
+// 255): a workgroup's few dozen sites rarely share a key, and a shared key
+// only interleaves two sites.  The ranking is stable (ballots over the key
+// bits rank a wavefront's lanes, per-wavefront counts in LDS order the
+// wavefronts), so the assignment is deterministic.  smem holds nw * 256
+// counts, zeroed by the caller before a barrier, then 5 words per thread.
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void regroup_by_site(int* smem, const int nw, float3& q, int64_t& i, int& s)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int* wc = smem;                 // [nw][256]: counts, then starts
+    int* slot = smem + nw * 256;    // [blockDim][5]: x, y, z, i, s
+    const uint32_t d = s >= 0 ? ((uint32_t)s & 255u) : 255u;
+    uint64_t peers = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m1 = __ballot(bit);
+        peers &= bit ? m1 : ~m1;
+    }
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int rank = __popcll(peers & below);
+    if (rank == 0) wc[wid * 256 + (int)d] = __popcll(peers);
+    __syncthreads();
+    if (wid == 0) {
+        // lane l holds keys 4l..4l+3: totals, exclusive scan, per-wavefront starts
+        int t[4], tot = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            t[k] = 0;
+            for (int w = 0; w < nw; ++w) t[k] += wc[w * 256 + 4 * lane + k];
+            tot += t[k];
+        }
+        int inc = tot;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += y;
+        }
+        int start = inc - tot;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            for (int w = 0; w < nw; ++w) {
+                const int c = wc[w * 256 + 4 * lane + k];
+                wc[w * 256 + 4 * lane + k] = start;
+                start += c;
+            }
+        }
+    }
+    __syncthreads();
+    const int pos = wc[wid * 256 + (int)d] + rank;
+    slot[5 * pos] = __float_as_int(q.x);
+    slot[5 * pos + 1] = __float_as_int(q.y);
+    slot[5 * pos + 2] = __float_as_int(q.z);
+    slot[5 * pos + 3] = (int)i;
+    slot[5 * pos + 4] = s;
+    __syncthreads();
+    const int me = (int)threadIdx.x;
+    q = make_float3(__int_as_float(slot[5 * me]), __int_as_float(slot[5 * me + 1]), __int_as_float(slot[5 * me + 2]));
+    i = slot[5 * me + 3];
+    s = slot[5 * me + 4];
+}
+
+// LDS of regroup_by_site for a workgroup of `block` threads, in ints.
+__host__ __device__ inline int regroup_lds_ints(int block) { return (block / 64) * 256 + block * 5; }
+
 // Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
 // b mod x).  Remapping block b to logical block (b mod x) * per + b / x gives
 // every XCD one contiguous range of the sorted points, so each XCD's L2 sees
@@ -701,27 +797,64 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
     const int64_t j = xcd_block(a.xcds, per) * blockDim.x + threadIdx.x;
     const bool valid = j < a.n;
     const int64_t i = valid ? (a.perm ? (int64_t)a.perm[j] : j) : 0;
-    if (!kFused) {
-        run_query<false, kCtr>(m, valid, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, nullptr, nullptr,
-                               DirectAcc{nullptr}, a.ctr);
-        return;
-    }
-    // fused: vertex gradients combined per workgroup in an LDS table,
-    // flushed once all its wavefronts are done (every thread reaches both
-    // barriers); without dL/dV there is no table and no barrier
-    extern __shared__ int acc_smem[];
-    const LdsAcc acc{a.grad_v, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
-    if (!a.grad_v) {
-        run_query<true, kCtr>(m, valid, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist,
-                              a.grad_q, acc, a.ctr);
-        return;
-    }
-    acc.init();
+    // The walk, then the workgroup's queries regrouped by located site (see
+    // regroup_by_site), then the list scans.  LDS: the regroup's area, then
+    // (fused with dL/dV) the table of vertex gradients, flushed once the
+    // workgroup is done.
+    extern __shared__ int smem[];
+    const int nw = (int)(blockDim.x >> 6);
+    int* rg_smem = smem;
+    int* acc_smem = smem + regroup_lds_ints((int)blockDim.x);
+    const bool gv = kFused && a.grad_v;
+    const LdsAcc acc{gv ? a.grad_v : nullptr, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
+    for (int k = threadIdx.x; k < nw * 256; k += blockDim.x) rg_smem[k] = 0;
+    if (gv) acc.init();
     __syncthreads();
-    run_query<true, kCtr>(m, valid, a.q_sorted ? j : i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q,
-                          acc, a.ctr);
-    __syncthreads();
-    acc.flush();
+    const int64_t iq = a.q_sorted ? j : i;
+    float3 q = make_float3(0.f, 0.f, 0.f);
+    if (valid) q = make_float3(a.q[3 * iq], a.q[3 * iq + 1], a.q[3 * iq + 2]);
+    const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
+    int s = -1;
+    float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
+    int4 rg = make_int4(0, 0, 0, 0);
+    if (finite && in_domain(m, q)) {
+        unsigned long long steps = 0, adj_read = 0;
+        if (m.oct) {
+            s = octree_locate(m, q, steps);
+            sp = m.site_rec[2 * s];
+            rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        } else {
+            s = locate<kCtr>(m, q, steps, adj_read, sp, rg);
+        }
+        if (kCtr) {
+            atomicAdd(&a.ctr[CTR_WALK_STEPS], steps);
+            atomicAdd(&a.ctr[CTR_ADJ_READ], adj_read);
+        }
+    }
+    // A workgroup holding a list longer than one lane's scan budget is left
+    // as it is: its wavefronts complete long lists one after the other, and
+    // gathering the lanes of such a site into one wavefront would queue all
+    // their scans there.
+    int64_t i2 = valid ? i : -1;
+    if (!__syncthreads_or(s >= 0 && rg.w - rg.z > kSerialBudget)) {
+        regroup_by_site(rg_smem, nw, q, i2, s);
+        if (s >= 0) {
+            sp = m.site_rec[2 * s];
+            rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        }
+    }
+    const bool valid2 = i2 >= 0;
+    const bool finite2 = valid2 && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
+    QueryCounts n;
+    Best b{kInf, -1, 0.f, 0.f};
+    int resume = -1;
+    if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n.list_read, n.exact, n.list_len);
+    finish_query<kFused, kCtr>(m, valid2, q, finite2, s, b, resume, valid2 ? i2 : 0, a.dist, a.tri, a.closest,
+                               a.grad_dist, a.grad_q, acc, a.ctr, n);
+    if (gv) {
+        __syncthreads();
+        acc.flush();
+    }
 }
 
 // Persistent batched kernel: each wavefront takes work items (up to `tile`
@@ -1165,14 +1298,18 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
     const unsigned g = (unsigned)(((nb + x - 1) / x) * x);
     FwdArgs args = a;
     args.xcds = x;
+    const size_t rg_bytes = 4 * (size_t)regroup_lds_ints(block);
     if (fused) {
-        args.acc_slots = acc_slots_for(block);
-        const size_t lds = a.grad_v ? acc_lds_bytes(args.acc_slots) : 0;
+        // the table within 64 KB of LDS together with the regroup's area
+        int slots = acc_slots_for(block);
+        while (slots > 64 && rg_bytes + acc_lds_bytes(slots) > 65536) slots >>= 1;
+        args.acc_slots = slots;
+        const size_t lds = rg_bytes + (a.grad_v ? acc_lds_bytes(slots) : 0);
         if (counters) fwd_kernel<true, true><<<g, block, lds, st>>>(m, args);
         else fwd_kernel<true, false><<<g, block, lds, st>>>(m, args);
     } else {
-        if (counters) fwd_kernel<false, true><<<g, block, 0, st>>>(m, args);
-        else fwd_kernel<false, false><<<g, block, 0, st>>>(m, args);
+        if (counters) fwd_kernel<false, true><<<g, block, rg_bytes, st>>>(m, args);
+        else fwd_kernel<false, false><<<g, block, rg_bytes, st>>>(m, args);
     }
     return hipGetLastError();
 }
