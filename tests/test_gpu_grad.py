@@ -246,3 +246,26 @@ def test_backward_table_flushes(dev, c3):
     for gv in (gv0, gv1):
         s = to_np(gq0).astype(np.float64).sum(0) + to_np(gv).astype(np.float64).sum(0)
         assert np.linalg.norm(s) <= 1e-4 * np.abs(to_np(gq0)).sum()
+
+
+def test_fused_block_sizes(dev, c3):
+    """The fused kernel's LDS holds the regroup area and, with dL/dV, the
+    vertex-gradient table (shrunk to fit 64 KB at 1,024 threads): every
+    workgroup size gives the same outputs and dL/dq bit for bit, and dL/dV up
+    to the order of float32 additions."""
+    c, m = c3
+    q = torch.from_numpy(c["Q"][:200000]).cuda()
+    g = torch.from_numpy(c["G"][:200000]).cuda()
+    outs = {}
+    for bs in (256, 64, 1024):
+        m.set_query_config(block_size=bs)
+        gv = torch.zeros((len(m.V), 3), device="cuda")
+        d, t, cl, gq = dev.query_fused(m, q, g, grad_vertices=gv)
+        torch.cuda.synchronize()
+        outs[bs] = (d, t, cl, gq, gv)
+    m.set_query_config(block_size=256)
+    ref = outs[256]
+    for bs in (64, 1024):
+        for a, b in zip(ref[:4], outs[bs][:4]):
+            assert torch.equal(a, b), bs
+        assert rel_err(to_np(outs[bs][4]), to_np(ref[4])) <= 1e-5, bs
