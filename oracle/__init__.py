@@ -50,6 +50,11 @@ def _load():
         lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_point_triangle_sq.argtypes = [P, P, P, P, P, P]
         lib.oracle_point_triangle_sq.restype = ctypes.c_double
+        lib.oracle_tree_build.argtypes = [P, i64, P, i64]
+        lib.oracle_tree_build.restype = P
+        lib.oracle_tree_free.argtypes = [P]
+        lib.oracle_tree_query.argtypes = [P, P, i64, P, P, P, ctypes.c_int]
+        lib.oracle_tree_query.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -86,6 +91,49 @@ def distance(V, F, Q, n_threads=0, want_closest=True):
     used = _load().oracle_bruteforce(_p(V), len(V), _p(F), len(F), _p(Q), n, _p(d), _p(tri),
                                      _p(p), int(n_threads))
     return d, tri, p, used
+
+
+class ExactTree:
+    """Tier-B oracle: the same exact FP64 result as ``distance`` (distance,
+    lowest-index triangle, closest point, bit for bit), found by
+    branch-and-bound over the oracle's own box tree of the triangles, for
+    query sets too large for the brute force."""
+
+    def __init__(self, V, F):
+        self.V, self.F = _f32(V), _i32(F)
+        self._h = _load().oracle_tree_build(_p(self.V), len(self.V), _p(self.F), len(self.F))
+        if not self._h:
+            raise MemoryError("oracle tree build failed")
+
+    def distance(self, Q, n_threads=0, want_closest=True):
+        """``(d, tri, closest, threads_used)`` as ``distance``."""
+        Q = _f32(Q)
+        n = len(Q)
+        d = np.empty(n, np.float64)
+        tri = np.empty(n, np.int32)
+        p = np.empty((n, 3), np.float64) if want_closest else None
+        used = _load().oracle_tree_query(self._h, _p(Q), n, _p(d), _p(tri), _p(p), int(n_threads))
+        return d, tri, p, used
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().oracle_tree_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def distance_exact(V, F, Q, n_threads=0, want_closest=True):
+    """Tier-B oracle in one call: builds the tree, answers ``Q``."""
+    t = ExactTree(V, F)
+    try:
+        return t.distance(Q, n_threads=n_threads, want_closest=want_closest)
+    finally:
+        t.close()
 
 
 def point_triangle(q, a, b, c):

@@ -280,3 +280,246 @@ void oracle_nearest_point(const float *P, int64_t nP, const float *Q, int64_t nQ
         if (out_d) out_d[i] = sqrt(best);
     }
 }
+
+/* ------------------------------------------------------------------------
+ * Tier B: the same definition evaluated by an exact branch-and-bound over an
+ * axis-aligned bounding-box tree of the triangles, for query sets too large
+ * for the brute force.  Nothing in it departs from the definition above: a
+ * subtree is skipped only when its box lies farther from q than the best
+ * distance so far plus a slack (1e-12 of the mesh scale) that covers the
+ * rounding of both the box distance and the triangle distances, and every
+ * triangle that is evaluated goes through oracle_point_triangle_sq with the
+ * rule "smaller squared distance, or equal with a smaller index, wins".
+ * The result is therefore the brute force's, bit for bit: the same
+ * distance, the same lowest-index triangle and the same closest point.
+ * The tree is the oracle's own (median split of triangle centroids along
+ * the widest axis, at most 4 triangles per leaf).
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    double lo[3], hi[3];
+    int64_t a, b; /* leaf: b < 0, triangles perm[a .. a - b - 1]; inner: children a, b */
+} onode;
+
+typedef struct {
+    const float *V;
+    const int32_t *F;
+    int64_t nT;
+    onode *nodes;
+    int64_t n_nodes;
+    int32_t *perm;
+    double *cen;  /* 3 per triangle, centroid (split key) */
+    double *tv;   /* 9 per leaf slot: the triangle's vertices, in leaf order */
+    double *tb;   /* 6 per leaf slot: the triangle's box (lo, hi) */
+    double slack;
+} otree;
+
+static int g_sort_axis; /* used only during the (serial) build */
+static const double *g_sort_cen;
+
+static int cmp_cen(const void *x, const void *y)
+{
+    double a = g_sort_cen[3 * (int64_t)*(const int32_t *)x + g_sort_axis];
+    double b = g_sort_cen[3 * (int64_t)*(const int32_t *)y + g_sort_axis];
+    if (a < b) return -1;
+    if (a > b) return 1;
+    return (*(const int32_t *)x > *(const int32_t *)y) - (*(const int32_t *)x < *(const int32_t *)y);
+}
+
+static void tri_box(const otree *t, int32_t f, double lo[3], double hi[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = INFINITY;
+        hi[k] = -INFINITY;
+    }
+    for (int j = 0; j < 3; ++j) {
+        double v[3];
+        load_vertex(t->V, t->F[3 * (int64_t)f + j], v);
+        for (int k = 0; k < 3; ++k) {
+            if (v[k] < lo[k]) lo[k] = v[k];
+            if (v[k] > hi[k]) hi[k] = v[k];
+        }
+    }
+}
+
+static int64_t build_node(otree *t, int64_t first, int64_t count)
+{
+    int64_t me = t->n_nodes++;
+    onode *n = &t->nodes[me];
+    for (int k = 0; k < 3; ++k) {
+        n->lo[k] = INFINITY;
+        n->hi[k] = -INFINITY;
+    }
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = first; i < first + count; ++i) {
+        double lo[3], hi[3];
+        int32_t f = t->perm[i];
+        tri_box(t, f, lo, hi);
+        for (int k = 0; k < 3; ++k) {
+            if (lo[k] < n->lo[k]) n->lo[k] = lo[k];
+            if (hi[k] > n->hi[k]) n->hi[k] = hi[k];
+            double c = t->cen[3 * (int64_t)f + k];
+            if (c < clo[k]) clo[k] = c;
+            if (c > chi[k]) chi[k] = c;
+        }
+    }
+    if (count <= 4) {
+        n->a = first;
+        n->b = -count;
+        return me;
+    }
+    int axis = 0;
+    for (int k = 1; k < 3; ++k)
+        if (chi[k] - clo[k] > chi[axis] - clo[axis]) axis = k;
+    g_sort_axis = axis;
+    g_sort_cen = t->cen;
+    qsort(t->perm + first, (size_t)count, sizeof(int32_t), cmp_cen);
+    int64_t half = count / 2;
+    int64_t left = build_node(t, first, half);
+    int64_t right = build_node(t, first + half, count - half);
+    t->nodes[me].a = left;
+    t->nodes[me].b = right;
+    return me;
+}
+
+/* Build the tree of mesh (V, F).  V and F must stay alive while the tree is
+ * used.  Returns NULL on allocation failure. */
+void *oracle_tree_build(const float *V, int64_t nV, const int32_t *F, int64_t nT)
+{
+    otree *t = (otree *)calloc(1, sizeof(otree));
+    if (!t) return NULL;
+    t->V = V;
+    t->F = F;
+    t->nT = nT;
+    t->perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nT > 0 ? nT : 1));
+    t->cen = (double *)malloc(sizeof(double) * 3 * (size_t)(nT > 0 ? nT : 1));
+    t->nodes = (onode *)malloc(sizeof(onode) * (size_t)(2 * nT + 1));
+    t->tv = (double *)malloc(sizeof(double) * 9 * (size_t)(nT > 0 ? nT : 1));
+    t->tb = (double *)malloc(sizeof(double) * 6 * (size_t)(nT > 0 ? nT : 1));
+    if (!t->perm || !t->cen || !t->nodes || !t->tv || !t->tb) {
+        free(t->perm);
+        free(t->cen);
+        free(t->nodes);
+        free(t->tv);
+        free(t->tb);
+        free(t);
+        return NULL;
+    }
+    double scale = 0.0;
+    for (int64_t i = 0; i < nV; ++i)
+        for (int k = 0; k < 3; ++k) {
+            double a = fabs((double)V[3 * i + k]);
+            if (a > scale) scale = a;
+        }
+    t->slack = 1e-12 * (scale > 0.0 ? scale : 1.0);
+    for (int64_t f = 0; f < nT; ++f) {
+        t->perm[f] = (int32_t)f;
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < 3; ++j) s += (double)V[3 * (int64_t)F[3 * f + j] + k];
+            t->cen[3 * f + k] = s / 3.0;
+        }
+    }
+    if (nT > 0) build_node(t, 0, nT);
+    for (int64_t k = 0; k < nT; ++k) {
+        int32_t f = t->perm[k];
+        for (int j = 0; j < 3; ++j) load_vertex(V, F[3 * (int64_t)f + j], &t->tv[9 * k + 3 * j]);
+        tri_box(t, f, &t->tb[6 * k], &t->tb[6 * k + 3]);
+    }
+    return t;
+}
+
+void oracle_tree_free(void *h)
+{
+    otree *t = (otree *)h;
+    if (!t) return;
+    free(t->perm);
+    free(t->cen);
+    free(t->nodes);
+    free(t->tv);
+    free(t->tb);
+    free(t);
+}
+
+static double box_dist2(const double q[3], const double lo[3], const double hi[3])
+{
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double d = 0.0;
+        if (q[k] < lo[k]) d = lo[k] - q[k];
+        else if (q[k] > hi[k]) d = q[k] - hi[k];
+        s += d * d;
+    }
+    return s;
+}
+
+/* True when a box at squared distance lb can still hold a triangle at most
+ * as far as the best squared distance so far. */
+static int may_hold(double lb, double best, double slack)
+{
+    return best == INFINITY || sqrt(lb) <= sqrt(best) + slack;
+}
+
+/*
+ * Exact distance of each query by branch-and-bound over the tree; outputs
+ * as oracle_bruteforce (identical values).  Returns the threads used.
+ */
+int oracle_tree_query(const void *h, const float *Q, int64_t nQ, double *out_d, int32_t *out_tri,
+                      double *out_p, int n_threads)
+{
+    const otree *t = (const otree *)h;
+    int used = set_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < nQ; ++i) {
+        double q[3] = {(double)Q[3 * i + 0], (double)Q[3 * i + 1], (double)Q[3 * i + 2]};
+        double best = INFINITY;
+        int32_t bt = -1;
+        if (t->nT > 0 && isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2])) {
+            int64_t stack[128];
+            int sp = 0;
+            stack[sp++] = 0;
+            while (sp > 0) {
+                const onode *n = &t->nodes[stack[--sp]];
+                if (!may_hold(box_dist2(q, n->lo, n->hi), best, t->slack)) continue;
+                if (n->b < 0) {
+                    for (int64_t k = n->a; k < n->a - n->b; ++k) {
+                        /* the triangle's own box bounds it like a node's */
+                        if (!may_hold(box_dist2(q, &t->tb[6 * k], &t->tb[6 * k + 3]), best, t->slack)) continue;
+                        int32_t f = t->perm[k];
+                        const double *v = &t->tv[9 * k];
+                        double p[3], lam[3];
+                        double d2 = oracle_point_triangle_sq(q, v, v + 3, v + 6, p, lam);
+                        if (d2 < best || (d2 == best && f < bt)) {
+                            best = d2;
+                            bt = f;
+                        }
+                    }
+                } else {
+                    /* nearer child on top of the stack */
+                    const onode *na = &t->nodes[n->a], *nb = &t->nodes[n->b];
+                    double la = box_dist2(q, na->lo, na->hi), lb = box_dist2(q, nb->lo, nb->hi);
+                    int64_t near = la <= lb ? n->a : n->b, far = la <= lb ? n->b : n->a;
+                    if (sp + 2 > 128) abort(); /* depth is about log2(nT): never reached */
+                    stack[sp++] = far;
+                    stack[sp++] = near;
+                }
+            }
+        }
+        double bp[3] = {NAN, NAN, NAN};
+        if (bt >= 0) {
+            double a[3], b[3], c[3], lam[3];
+            load_vertex(t->V, t->F[3 * (int64_t)bt + 0], a);
+            load_vertex(t->V, t->F[3 * (int64_t)bt + 1], b);
+            load_vertex(t->V, t->F[3 * (int64_t)bt + 2], c);
+            oracle_point_triangle_sq(q, a, b, c, bp, lam);
+        }
+        out_d[i] = bt >= 0 ? sqrt(best) : NAN;
+        out_tri[i] = bt;
+        if (out_p) {
+            out_p[3 * i + 0] = bp[0];
+            out_p[3 * i + 1] = bp[1];
+            out_p[3 * i + 2] = bp[2];
+        }
+    }
+    return used;
+}

@@ -365,3 +365,102 @@ def test_point_set_distance_concentric_spheres_bounds():
     assert d.min() >= 1.0 - 1e-6 and d.max() <= 2.0 - rho + 1e-6
     r = oracle.point_set_distance(V, F, A)
     assert abs(r["max"] - d.max()) == 0 and r["count"] == len(A)
+
+
+# -------------------------------------------- per-triangle helper closed forms
+
+# One right triangle a = (0,0,0), b = (1,0,0), c = (0,1,0) in the plane z = 0,
+# placed in each coordinate plane and translated by exactly representable
+# offsets, so that every closed form below is exact in FP64.  Each point is
+# (local x, local y, height h) with its region, the expected closest point
+# (local) and distance.  A helper that returned 0, or too small or too large
+# a value, or the closest point of another region, fails.
+_REGION_CASES = [
+    # face: straight above an interior point
+    ((0.25, 0.5, 0.75), "face", (0.25, 0.5, 0.0)),
+    ((0.125, 0.125, -2.0), "face", (0.125, 0.125, 0.0)),
+    # edge ab (y = 0), edge ca (x = 0), edge bc (x + y = 1)
+    ((0.5, -0.75, 0.5), "ab", (0.5, 0.0, 0.0)),
+    ((-0.5, 0.25, -1.0), "ca", (0.0, 0.25, 0.0)),
+    ((0.75, 0.75, 0.25), "bc", (0.5, 0.5, 0.0)),
+    # vertices a, b, c
+    ((-0.5, -0.25, 1.0), "a", (0.0, 0.0, 0.0)),
+    ((1.5, -0.5, -0.25), "b", (1.0, 0.0, 0.0)),
+    ((-0.25, 1.75, 0.5), "c", (0.0, 1.0, 0.0)),
+]
+
+
+def _placed_triangle(plane, offset, scale):
+    """Vertices and the local->world map of the unit right triangle placed
+    in coordinate plane ``plane`` (0: z = const, 1: x = const, 2: y = const)."""
+    axes = [(0, 1, 2), (1, 2, 0), (2, 0, 1)][plane]
+
+    def world(u):
+        w = np.zeros(3)
+        for k in range(3):
+            w[axes[k]] = scale * u[k]
+        return w + np.asarray(offset)
+
+    return world
+
+
+@pytest.mark.parametrize("plane", [0, 1, 2])
+@pytest.mark.parametrize("offset,scale", [((0.0, 0.0, 0.0), 1.0), ((2.5, -1.25, 0.375), 4.0),
+                                          ((-100.0, 50.0, 12.0), 0.0625)])
+def test_distance_to_triangles_closed_forms(plane, offset, scale):
+    world = _placed_triangle(plane, offset, scale)
+    V = np.array([world((0, 0, 0)), world((1, 0, 0)), world((0, 1, 0))], np.float32)
+    F = np.array([[0, 1, 2]], np.int32)
+    assert np.array_equal(V.astype(np.float64),
+                          np.array([world((0, 0, 0)), world((1, 0, 0)), world((0, 1, 0))]))
+    Q = np.array([world(u) for u, _, _ in _REGION_CASES])
+    P = np.array([world(p) for _, _, p in _REGION_CASES])
+    exp = np.linalg.norm(Q - P, axis=1)
+    assert np.all(exp > 0.1 * scale)
+    assert np.array_equal(Q.astype(np.float32).astype(np.float64), Q)   # exact in float32
+    tri = np.zeros(len(Q), np.int32)
+    d, p, lam = oracle.distance_to_triangles(V, F, Q.astype(np.float32), tri)
+    assert np.max(np.abs(d - exp)) <= 1e-14 * max(1.0, np.abs(Q).max())
+    assert np.max(np.abs(p - P)) <= 1e-13 * max(1.0, np.abs(Q).max())
+    assert np.allclose(lam.sum(1), 1.0, atol=1e-14) and lam.min() >= 0.0
+    assert np.max(np.abs(lam @ V.astype(np.float64) - P)) <= 1e-12 * max(1.0, np.abs(Q).max())
+    d64 = oracle.distance_to_triangles64(V, F, Q, tri)
+    assert np.max(np.abs(d64 - exp)) <= 1e-14 * max(1.0, np.abs(Q).max())
+    # the float64 variant takes points that are not float32 values
+    Q2 = Q + np.array([1e-9, -3e-10, 7e-10]) * scale
+    P2 = np.array([world(p) for _, _, p in _REGION_CASES])
+    d2 = oracle.distance_to_triangles64(V, F, Q2, tri)
+    assert np.max(np.abs(d2 - np.linalg.norm(Q2 - P2, axis=1))) <= 4e-9 * scale
+
+
+def test_distance_to_triangles_picks_the_given_triangle():
+    """Two triangles at different known distances: each query is measured
+    against the triangle named for it, not the nearer one."""
+    V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 2], [1, 0, 2], [0, 1, 2]], np.float32)
+    F = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    Q = np.array([[0.25, 0.25, 0.5], [0.25, 0.25, 0.5], [0.25, 0.25, 3.0]], np.float32)
+    tri = np.array([0, 1, 0], np.int32)
+    d, p, _ = oracle.distance_to_triangles(V, F, Q, tri)
+    assert np.array_equal(d, [0.5, 1.5, 3.0])
+    assert np.array_equal(p, [[0.25, 0.25, 0.0], [0.25, 0.25, 2.0], [0.25, 0.25, 0.0]])
+    d64 = oracle.distance_to_triangles64(V, F, Q.astype(np.float64), tri)
+    assert np.array_equal(d64, [0.5, 1.5, 3.0])
+
+
+def test_distance_to_triangles_matches_region_walk_on_random_meshes():
+    rng = np.random.default_rng(11)
+    V = rng.normal(size=(60, 3)).astype(np.float32)
+    # distinct corners (the region walk divides by zero on a repeated one)
+    F = np.array([rng.choice(60, 3, replace=False) for _ in range(200)], np.int32)
+    Q = (rng.normal(size=(2000, 3)) * 2).astype(np.float32)
+    tri = rng.integers(0, 200, 2000).astype(np.int32)
+    d, p, _ = oracle.distance_to_triangles(V, F, Q, tri)
+    Vd = V.astype(np.float64)
+    ref = np.array([np.linalg.norm(Q[i].astype(np.float64) - ericson_region_walk(Q[i].astype(np.float64),
+                                                                                *Vd[F[tri[i]]]))
+                    for i in range(len(Q))])
+    assert np.max(np.abs(d - ref)) <= 1e-12
+    P = Q.astype(np.float64) + rng.normal(size=(2000, 3)) * 1e-3
+    d64 = oracle.distance_to_triangles64(V, F, P, tri)
+    ref64 = np.array([np.linalg.norm(P[i] - ericson_region_walk(P[i], *Vd[F[tri[i]]])) for i in range(len(P))])
+    assert np.max(np.abs(d64 - ref64)) <= 1e-12
