@@ -129,8 +129,12 @@ int32_t p2m_destroy(p2m_handle h);
  *   d_out_dist:    device, n float32 (required); NaN for a non-finite point
  *   d_out_tri:     device, n int32 (nullable); caller's triangle id, -1 for NaN
  *   d_out_closest: device, n x 3 float32 (nullable); closest point on the mesh
- * Calls sharing one handle must not run concurrently on different streams
- * (the handle's query workspace is reused). */
+ * The handle is read-only after p2m_build: calls on different streams may
+ * run concurrently, each stream getting its own scratch memory (the query
+ * sort's workspace, about 16 B per point, allocated on a stream's first call
+ * and grown as needed; held until p2m_destroy).  Calls on one stream run in
+ * stream order; calls from several host threads are serialised while they
+ * enqueue. */
 int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
                   int32_t* d_out_tri, float* d_out_closest, void* stream);
 
@@ -145,10 +149,33 @@ int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_d
  *             distances, number of points counted; non-finite points (NaN
  *             distance) are left out.  n = 0 (or no finite point) gives
  *             max = -1, index = -1, sums and count 0.
- * Runs p2m_query's sort and search into a handle-owned buffer (n floats,
- * allocated on first use and grown as needed; same concurrency rule as
- * p2m_query) and two reduction kernels, all on `stream`. */
+ * Runs p2m_query's sort and search into a buffer of the stream's scratch
+ * (n floats, allocated on first use and grown as needed; see p2m_query) and
+ * two reduction kernels, all on `stream`. */
 int32_t p2m_point_set_distance(p2m_handle h, const float* d_points, int64_t n, double* d_out, void* stream);
+
+/* Distances between two meshes A (handle a) and B (handle b) measured on
+ * point sets, built on the point query (Sec. 5 names mesh-to-mesh distance
+ * as an application; the measures are defined here): points on A against
+ * mesh B and points on B against mesh A, each reduced as in
+ * p2m_point_set_distance.
+ *   d_points_a: device, n_a x 3 float32 points on A; NULL with n_a = 0 for
+ *               A's referenced vertices (every vertex some triangle uses, in
+ *               index order: the exact vertex-to-mesh distances)
+ *   d_points_b: likewise for B
+ *   d_out:      device, 6 float64: [0] one-sided Hausdorff distance A to B
+ *               (largest distance of A's points to B), [1] B to A, [2] the
+ *               symmetric Hausdorff distance max([0], [1]), [3] the Chamfer
+ *               distance mean_A d + mean_B d, [4] the squared Chamfer
+ *               distance mean_A d^2 + mean_B d^2, [5] the number of points
+ *               counted.  Points with a non-finite coordinate are left out;
+ *               a side without points gives -1 in [0] or [1] and adds 0 to
+ *               [3] and [4].
+ * Both handles must be on one device.  Enqueues two point-set distances and
+ * one small kernel on `stream`; the two reductions are kept in a's scratch
+ * of that stream (80 bytes). */
+int32_t p2m_mesh_distance(p2m_handle a, p2m_handle b, const float* d_points_a, int64_t n_a,
+                          const float* d_points_b, int64_t n_b, double* d_out, void* stream);
 
 /* The two halves of p2m_query, for callers that sort once and query several
  * times (or time the search kernel alone).
@@ -178,7 +205,13 @@ int32_t p2m_query_ordered(p2m_handle h, const float* d_points, const int32_t* d_
  *   dL/dq_i = g_i (q_i - p_i) / d_i;
  *   dL/dv_k += -g_i lambda_k (q_i - p_i) / d_i for the 3 vertices of tri_i,
  * with lambda the barycentrics of the closest point p_i; 0 when d_i = 0.
- *   d_tri, d_closest, d_dist: the forward outputs for the same points
+ *   d_tri:           the forward's triangle ids for the same points
+ *   d_closest, d_dist: the forward's closest points and distances (device,
+ *                    nullable: both or neither).  Given, dL/dq is formed
+ *                    from them and the triangle is read only for the
+ *                    barycentrics of dL/dV (so dL/dq alone reads no
+ *                    triangle); NULL, the closest point is recomputed from
+ *                    the triangle, exactly as the forward found it.
  *   d_grad_dist:     device, n float32
  *   d_grad_points:   device, n x 3 float32 (nullable), overwritten
  *   d_grad_vertices: device, n_vertices x 3 float32 (nullable), accumulated
@@ -209,12 +242,27 @@ int32_t p2m_get_query_config(p2m_handle h, p2m_query_config* out);
 int32_t p2m_set_query_config(p2m_handle h, const p2m_query_config* cfg);
 
 /* Instrumented forward (same results as p2m_query) that also accumulates,
- * into d_counters (device, 6 uint64, caller-zeroed): walk steps, adjacency
+ * into d_counters (device, 7 uint64, caller-zeroed): walk steps, adjacency
  * entries read, list entries read, exact point-triangle tests, queries
- * answered by the fallback, sum of the located site's list length. */
+ * answered by the exact BVH fallback (points outside the domain box, and
+ * walks stopped at the step cap), sum of the located site's list length,
+ * walks stopped at the step cap (4,096 steps; not reached on a valid
+ * Delaunay graph). */
 int32_t p2m_query_counters(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
                            int32_t* d_out_tri, float* d_out_closest,
                            unsigned long long* d_counters, void* stream);
+
+/* p2m_query_counters that also records which items of the search structure
+ * the launch reads, and writes to h_items (host, 7 int64) the number of
+ * distinct items read per array: site records (32 B each), adjacency
+ * entries (16 B), list spheres (16 B), list records (48 B), seed-grid cells
+ * (4 B), triangle records of the fallback (48 B), fallback BVH nodes (32 B).
+ * Their sum times the sizes is the structure's share of the launch's
+ * compulsory bytes.  Synchronous: waits for `stream`; allocates and frees
+ * one flag byte per item. */
+int32_t p2m_query_touched(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
+                          int32_t* d_out_tri, float* d_out_closest, unsigned long long* d_counters,
+                          int64_t* h_items, void* stream);
 
 /* Host-side inspection of the built structure (no GPU needed).
  * p2m_host_sites: n_sites x 3 float32 positions and is-auxiliary flags

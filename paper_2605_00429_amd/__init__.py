@@ -16,8 +16,8 @@ from . import _lib
 from ._lib import P2MError, check, lib
 
 __all__ = ["Mesh", "Batch", "distance", "query", "query_backward", "query_fused", "point_set_distance",
-           "hausdorff", "chamfer",
-           "query_counters", "sort_points", "query_sorted", "query_ordered", "P2MError", "build_opts"]
+           "mesh_distance", "hausdorff", "chamfer", "query_counters", "query_touched", "sort_points",
+           "query_sorted", "query_ordered", "P2MError", "build_opts"]
 
 
 def build_opts(**kw):
@@ -206,34 +206,42 @@ def point_set_distance(mesh, points, stream=None):
     return {"max": v[0], "argmax": int(v[1]), "sum": v[2], "sum_sq": v[3], "count": int(v[4])}
 
 
-def _surface_points(mesh, points):
+def mesh_distance(mesh_a, mesh_b, points_a=None, points_b=None, stream=None):
+    """Distances between two meshes measured on point sets of each
+    (``p2m_mesh_distance``): ``points_a`` on A against mesh B and
+    ``points_b`` on B against mesh A, by default each mesh's referenced
+    vertices.  Returns a dict with the one-sided Hausdorff distances
+    ``hausdorff_ab`` and ``hausdorff_ba``, the symmetric ``hausdorff``, the
+    Chamfer distances ``chamfer`` (means of d) and ``chamfer_sq`` (means of
+    d^2), and ``count``, the number of points counted."""
     import torch
-    if points is not None:
-        return points
-    # the referenced vertices: exact vertex-to-mesh distances
-    V = mesh.V[np.unique(mesh.F)]
-    return torch.from_numpy(np.ascontiguousarray(V, dtype=np.float32)).to(mesh.device)
+    dev = mesh_a.device
+    if mesh_b.device != dev:
+        raise ValueError("both meshes must be on one device")
+    pa = _check_points(mesh_a, points_a) if points_a is not None else None
+    pb = _check_points(mesh_b, points_b) if points_b is not None else None
+    out = torch.empty(6, dtype=torch.float64, device=dev)
+    check(lib().p2m_mesh_distance(mesh_a.handle, mesh_b.handle, _ptr(pa), pa.shape[0] if pa is not None else 0,
+                                  _ptr(pb), pb.shape[0] if pb is not None else 0, _ptr(out), _stream(stream)))
+    v = out.cpu().tolist()
+    return {"hausdorff_ab": v[0], "hausdorff_ba": v[1], "hausdorff": v[2], "chamfer": v[3], "chamfer_sq": v[4],
+            "count": int(v[5])}
 
 
 def hausdorff(mesh_a, mesh_b, points_a=None, points_b=None, symmetric=True, stream=None):
     """Hausdorff distance between two meshes measured on point sets of each
     (``points_a`` on A, ``points_b`` on B; by default their referenced
     vertices).  One-sided (A to B) unless ``symmetric``."""
-    ab = point_set_distance(mesh_b, _surface_points(mesh_a, points_a).to(mesh_b.device), stream)["max"]
-    if not symmetric:
-        return ab
-    ba = point_set_distance(mesh_a, _surface_points(mesh_b, points_b).to(mesh_a.device), stream)["max"]
-    return max(ab, ba)
+    r = mesh_distance(mesh_a, mesh_b, points_a, points_b, stream)
+    return r["hausdorff"] if symmetric else r["hausdorff_ab"]
 
 
 def chamfer(mesh_a, mesh_b, points_a=None, points_b=None, squared=False, stream=None):
     """Chamfer distance: the mean distance from points of A to mesh B plus
     the mean distance from points of B to mesh A (mean squared distances
     with ``squared``)."""
-    key = "sum_sq" if squared else "sum"
-    ab = point_set_distance(mesh_b, _surface_points(mesh_a, points_a).to(mesh_b.device), stream)
-    ba = point_set_distance(mesh_a, _surface_points(mesh_b, points_b).to(mesh_a.device), stream)
-    return ab[key] / max(ab["count"], 1) + ba[key] / max(ba["count"], 1)
+    r = mesh_distance(mesh_a, mesh_b, points_a, points_b, stream)
+    return r["chamfer_sq"] if squared else r["chamfer"]
 
 
 def sort_points(mesh, points, want_sorted=False, stream=None):
@@ -293,27 +301,57 @@ def query_counters(mesh, points, stream=None):
     check(lib().p2m_query_counters(mesh.handle, _ptr(p), n, _ptr(dist), _ptr(tri), _ptr(closest),
                                    _ptr(ctr), _stream(stream)))
     c = ctr.cpu().tolist()
-    names = ["walk_steps", "adj_read", "list_read", "exact_tests", "fallback", "list_len"]
-    return dist, tri, closest, dict(zip(names, c))
+    return dist, tri, closest, dict(zip(COUNTER_NAMES, c))
 
 
-def query_backward(mesh, points, tri, grad_dist, grad_points=True, grad_vertices=None, order=None, stream=None):
+COUNTER_NAMES = ["walk_steps", "adj_read", "list_read", "exact_tests", "fallback", "list_len", "walk_capped"]
+# the structure arrays p2m_query_touched reports on, and the bytes of one item
+TOUCH_ITEMS = [("site_rec", 32), ("adjacency", 16), ("list_sphere", 16), ("list_record", 48), ("seed", 4),
+               ("fallback_triangle", 48), ("fallback_bvh_node", 32)]
+
+
+def query_touched(mesh, points, stream=None):
+    """Instrumented forward that also counts the distinct structure items the
+    launch reads (``p2m_query_touched``): ``(dist, tri, closest, counters,
+    items)`` with ``items`` a dict name -> (distinct items, bytes)."""
+    import torch
+    p = _check_points(mesh, points)
+    n = p.shape[0]
+    dist = torch.empty(n, dtype=torch.float32, device=p.device)
+    tri = torch.empty(n, dtype=torch.int32, device=p.device)
+    closest = torch.empty((n, 3), dtype=torch.float32, device=p.device)
+    ctr = torch.zeros(8, dtype=torch.int64, device=p.device)
+    items = (ctypes.c_int64 * 7)()
+    check(lib().p2m_query_touched(mesh.handle, _ptr(p), n, _ptr(dist), _ptr(tri), _ptr(closest), _ptr(ctr),
+                                  items, _stream(stream)))
+    c = ctr.cpu().tolist()
+    touched = {name: (int(items[k]), int(items[k]) * size) for k, (name, size) in enumerate(TOUCH_ITEMS)}
+    return dist, tri, closest, dict(zip(COUNTER_NAMES, c)), touched
+
+
+def query_backward(mesh, points, tri, grad_dist, grad_points=True, grad_vertices=None, order=None,
+                   closest=None, dist=None, stream=None):
     """Gradients of ``sum(grad_dist * dist)``: ``(dL/dpoints, dL/dV)``.
     ``grad_vertices`` may be a zeroed (nV, 3) tensor to accumulate into.
     ``order``: the visiting order ``sort_points`` gave for the forward pass
     (``p2m_query_backward_ordered``); without it the points are sorted again
-    when dL/dV is wanted."""
+    when dL/dV is wanted.  ``closest`` and ``dist`` (both or neither, not
+    with ``order``): the forward's outputs, from which dL/dq is formed."""
     import torch
     p = _check_points(mesh, points)
     n = p.shape[0]
     g = grad_dist.contiguous().to(torch.float32)
     gq = torch.empty((n, 3), dtype=torch.float32, device=p.device) if grad_points else None
     if order is not None:
+        if closest is not None or dist is not None:
+            raise ValueError("closest/dist are taken by the unordered backward only")
         check(lib().p2m_query_backward_ordered(mesh.handle, _ptr(p), _ptr(order), n, _ptr(tri.contiguous()),
                                                _ptr(g), _ptr(gq), _ptr(grad_vertices), _stream(stream)))
     else:
-        check(lib().p2m_query_backward(mesh.handle, _ptr(p), n, _ptr(tri.contiguous()), None, None, _ptr(g),
-                                       _ptr(gq), _ptr(grad_vertices), _stream(stream)))
+        cl = closest.contiguous() if closest is not None else None
+        dd = dist.contiguous() if dist is not None else None
+        check(lib().p2m_query_backward(mesh.handle, _ptr(p), n, _ptr(tri.contiguous()), _ptr(cl), _ptr(dd),
+                                       _ptr(g), _ptr(gq), _ptr(grad_vertices), _stream(stream)))
     return gq, grad_vertices
 
 

@@ -79,6 +79,8 @@ SIGNATURES = {
     "p2m_destroy": (_I32, [_VP]),
     "p2m_query": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP]),
     "p2m_point_set_distance": (_I32, [_VP, _VP, _I64, _VP, _VP]),
+    "p2m_mesh_distance": (_I32, [_VP, _VP, _VP, _I64, _VP, _I64, _VP, _VP]),
+    "p2m_query_touched": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP]),
     "p2m_query_backward": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "p2m_query_backward_ordered": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP]),
     "p2m_query_fused": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -44,6 +46,20 @@ struct DeviceGuard {
 
 }  // namespace
 
+// Scratch memory of the calls made on one stream: the query sort's
+// workspace, and the distances and reduction partials of the point-set
+// reduction.  Each stream that queries a handle gets its own, so that calls
+// on different streams never share memory; a buffer is regrown only after
+// its own stream has finished with it.
+struct StreamScratch {
+    hipStream_t stream = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* rws = nullptr;
+    size_t rws_bytes = 0;
+    double* pair = nullptr;  // mesh distances: the two one-sided reductions (10 doubles)
+};
+
 struct p2m_handle_ {
     p2m::HostStructure H;
     int device = -1;
@@ -51,18 +67,22 @@ struct p2m_handle_ {
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
     p2m_query_config cfg{256, 1, 1, 0};
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    void* rws = nullptr;  // point-set distances and reduction partials
-    size_t rws_bytes = 0;
+    // the caller's referenced vertices (index order), for mesh distances
+    const float* ref_v = nullptr;
+    int64_t n_ref = 0;
+    std::recursive_mutex mu;  // guards `scratch` and the enqueues that use it
+    std::list<StreamScratch> scratch;  // a list: references stay valid as streams are added
 
     ~p2m_handle_()
     {
         if (device >= 0) {
             DeviceGuard g(device);
             for (void* p : allocs) (void)hipFree(p);
-            if (ws) (void)hipFree(ws);
-            if (rws) (void)hipFree(rws);
+            for (StreamScratch& sc : scratch) {
+                if (sc.ws) (void)hipFree(sc.ws);
+                if (sc.rws) (void)hipFree(sc.rws);
+                if (sc.pair) (void)hipFree(sc.pair);
+            }
         }
     }
 
@@ -82,14 +102,26 @@ struct p2m_handle_ {
         return (const T*)p;
     }
 
-    void upload_all()
+    void upload_all(const p2m_mesh_desc& mesh)
     {
         using namespace p2m;
         const HostStructure& h = H;
         static_assert(sizeof(SiteRec) == 32 && sizeof(ListRec) == 64, "device record layout");
         dm.site_rec = upload<float4>(h.site_rec.data(), h.site_rec.size() * sizeof(SiteRec));
         dm.adj = upload<float4>(h.adj.data(), h.adj.size() * 4);
-        dm.list_rec = upload<float4>(h.list_rec.data(), h.list_rec.size() * sizeof(ListRec));
+        // list entries split into a dense sphere array (what the scan reads
+        // for every entry) and the records at the same index
+        {
+            const size_t ne = h.list_rec.size();
+            std::vector<float> sph(4 * ne), rec(12 * ne);
+            for (size_t k = 0; k < ne; ++k) {
+                const ListRec& L = h.list_rec[k];
+                std::memcpy(&sph[4 * k], &L.cx, 16);
+                std::memcpy(&rec[12 * k], &L.ax, 48);
+            }
+            dm.list_sph = upload<float4>(sph.data(), sph.size() * 4);
+            dm.list_rec = upload<float4>(rec.data(), rec.size() * 4);
+        }
         dm.tri_rec = upload<float4>(h.tri_rec.data(), h.tri_rec.size() * 4);
         dm.tri_user = upload<int32_t>(h.tri_user.data(), h.tri_user.size() * 4);
         dm.tri_vid = upload<int4>(h.tri_vid.data(), h.tri_vid.size() * 4);
@@ -110,22 +142,60 @@ struct p2m_handle_ {
         dm.n_sites = h.n_sites;
         dm.n_tris = (int32_t)h.n_triangles;
         dm.n_vertices = (int32_t)h.n_vertices;
+        // referenced vertices in index order (the default point set of a
+        // mesh-to-mesh distance)
+        std::vector<char> used((size_t)mesh.n_vertices, 0);
+        for (int64_t k = 0; k < 3 * mesh.n_triangles; ++k) used[mesh.triangles[k]] = 1;
+        std::vector<float> rv;
+        for (int64_t v = 0; v < mesh.n_vertices; ++v)
+            if (used[v]) rv.insert(rv.end(), mesh.vertices + 3 * v, mesh.vertices + 3 * v + 3);
+        n_ref = (int64_t)rv.size() / 3;
+        ref_v = upload<float>(rv.data(), rv.size() * 4);
     }
 
-    // Grows the query workspace; waits for earlier work on `st` first.
-    int32_t ensure_ws(size_t bytes, hipStream_t st)
+    // This stream's scratch (created on first use); the caller holds mu.
+    StreamScratch& scratch_for(hipStream_t st)
     {
-        if (ws_bytes >= bytes) return P2M_OK;
+        for (StreamScratch& sc : scratch)
+            if (sc.stream == st) return sc;
+        scratch.push_back(StreamScratch{});
+        scratch.back().stream = st;
+        return scratch.back();
+    }
+
+    // Grows one scratch buffer of `st` to at least `bytes`; waits for earlier
+    // work on `st` first (the only stream that used it).  The caller holds mu.
+    int32_t grow(void*& buf, size_t& have, size_t bytes, hipStream_t st)
+    {
+        if (have >= bytes) return P2M_OK;
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        if (ws) (void)hipFree(ws);
-        ws = nullptr;
-        ws_bytes = 0;
+        if (buf) (void)hipFree(buf);
+        buf = nullptr;
+        have = 0;
         const size_t nb = bytes + bytes / 4;
-        e = hipMalloc(&ws, nb);
+        e = hipMalloc(&buf, nb);
         if (e != hipSuccess) return fail(P2M_ERR_OOM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
-        ws_bytes = nb;
+        have = nb;
         return P2M_OK;
+    }
+
+    // The sort workspace of `st`, at least `bytes` (caller holds mu).
+    int32_t ensure_ws(size_t bytes, hipStream_t st, void** out)
+    {
+        StreamScratch& sc = scratch_for(st);
+        const int32_t rc = grow(sc.ws, sc.ws_bytes, bytes, st);
+        *out = sc.ws;
+        return rc;
+    }
+
+    // The point-set reduction buffer of `st`, at least `bytes` (caller holds mu).
+    int32_t ensure_rws(size_t bytes, hipStream_t st, void** out)
+    {
+        StreamScratch& sc = scratch_for(st);
+        const int32_t rc = grow(sc.rws, sc.rws_bytes, bytes, st);
+        *out = sc.rws;
+        return rc;
     }
 };
 
@@ -185,7 +255,7 @@ int32_t p2m_build(const p2m_mesh_desc* mesh, const p2m_build_opts* opts, p2m_han
             const p2m::GpuListFn on_device = p2m::gpu_build_lists;
             p2m::build_host(*mesh, o, h->H, o.gpu_lists ? &on_device : nullptr);
             h->device = dev;
-            h->upload_all();
+            h->upload_all(*mesh);
         } else {
             p2m::build_host(*mesh, o, h->H);
         }
@@ -244,7 +314,7 @@ int32_t p2m_set_query_config(p2m_handle h, const p2m_query_config* c)
 
 static int32_t query_common(p2m_handle h, const float* q, int64_t n, float* dist, int32_t* tri, float* closest,
                             const float* g, float* gq, float* gv, unsigned long long* ctr, bool fused,
-                            void* stream)
+                            void* stream, const p2m::Touch* touch = nullptr)
 {
     if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
     if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
@@ -265,13 +335,16 @@ static int32_t query_common(p2m_handle h, const float* q, int64_t n, float* dist
     a.grad_q = gq;
     a.grad_v = gv;
     a.ctr = ctr;
+    if (touch) a.touch = *touch;
     a.xcds = h->cfg.xcd_groups;
+    std::lock_guard<std::recursive_mutex> lk(h->mu);
     if (h->cfg.reorder) {
         // The search gathers each point through the order: measured faster
         // than having the sort also write the points in visiting order.
-        int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st);
+        void* ws = nullptr;
+        int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st, &ws);
         if (rc != P2M_OK) return rc;
-        hipError_t e = p2m::launch_reorder(h->dm, q, n, h->cfg.sort_bits, h->ws, &a.perm, st);
+        hipError_t e = p2m::launch_reorder(h->dm, q, n, h->cfg.sort_bits, ws, &a.perm, st);
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
     }
     hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, fused, ctr != nullptr, st);
@@ -295,27 +368,57 @@ int32_t p2m_point_set_distance(p2m_handle h, const float* d_points, int64_t n, d
     if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
     DeviceGuard dg(h->device);
     hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::recursive_mutex> lk(h->mu);
     const size_t dist_bytes = ((size_t)n * sizeof(float) + 255) & ~(size_t)255;
     const size_t need = dist_bytes + 5 * sizeof(double) * (size_t)p2m::reduce_blocks(n);
-    if (h->rws_bytes < need) {
-        hipError_t e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        if (h->rws) (void)hipFree(h->rws);
-        h->rws = nullptr;
-        h->rws_bytes = 0;
-        e = hipMalloc(&h->rws, need + need / 4);
-        if (e != hipSuccess) return fail(P2M_ERR_OOM, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
-        h->rws_bytes = need + need / 4;
-    }
-    float* dist = (float*)h->rws;
-    double* part = (double*)((char*)h->rws + dist_bytes);
+    void* rws = nullptr;
+    int32_t rc = h->ensure_rws(need, st, &rws);
+    if (rc != P2M_OK) return rc;
+    float* dist = (float*)rws;
+    double* part = (double*)((char*)rws + dist_bytes);
     if (n > 0) {
-        const int32_t rc = query_common(h, d_points, n, dist, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                        false, stream);
+        rc = query_common(h, d_points, n, dist, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false, stream);
         if (rc != P2M_OK) return rc;
     }
     const hipError_t e = p2m::launch_reduce_dist(dist, n, part, d_out, st);
     if (e != hipSuccess) return hip_fail(e, "reduction launch");
+    return P2M_OK;
+}
+
+int32_t p2m_mesh_distance(p2m_handle a, p2m_handle b, const float* d_points_a, int64_t n_a,
+                          const float* d_points_b, int64_t n_b, double* d_out, void* stream)
+{
+    if (!a || !b) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (a->device < 0 || b->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (a->device != b->device) return fail(P2M_ERR_INVALID_ARG, "handles on different devices");
+    if (!d_out) return fail(P2M_ERR_INVALID_ARG, "null output");
+    if ((d_points_a && n_a < 0) || (d_points_b && n_b < 0)) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if ((!d_points_a && n_a != 0) || (!d_points_b && n_b != 0))
+        return fail(P2M_ERR_INVALID_ARG, "a point count without points (pass 0 with NULL for the vertices)");
+    const float* pa = d_points_a ? d_points_a : a->ref_v;
+    const int64_t na = d_points_a ? n_a : a->n_ref;
+    const float* pb = d_points_b ? d_points_b : b->ref_v;
+    const int64_t nb = d_points_b ? n_b : b->n_ref;
+    DeviceGuard dg(a->device);
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::recursive_mutex> lk(a->mu);
+    // the two one-sided reductions (5 doubles each), in a's scratch of this
+    // stream
+    StreamScratch& sc = a->scratch_for(st);
+    if (!sc.pair) {
+        const hipError_t e = hipMalloc(&sc.pair, 10 * sizeof(double));
+        if (e != hipSuccess) {
+            sc.pair = nullptr;
+            return fail(P2M_ERR_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+    }
+    double* pair = sc.pair;
+    int32_t rc = p2m_point_set_distance(b, pa, na, pair, stream);      // A's points against mesh B
+    if (rc != P2M_OK) return rc;
+    rc = p2m_point_set_distance(a, pb, nb, pair + 5, stream);  // B's points against mesh A
+    if (rc != P2M_OK) return rc;
+    const hipError_t e = p2m::launch_mesh_distance_combine(pair, pair + 5, d_out, st);
+    if (e != hipSuccess) return hip_fail(e, "combine launch");
     return P2M_OK;
 }
 
@@ -330,10 +433,12 @@ int32_t p2m_sort_points(p2m_handle h, const float* d_points, int64_t n, int32_t*
     if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
     DeviceGuard dg(h->device);
     hipStream_t st = (hipStream_t)stream;
-    int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st);
+    std::lock_guard<std::recursive_mutex> lk(h->mu);
+    void* ws = nullptr;
+    int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st, &ws);
     if (rc != P2M_OK) return rc;
     const int32_t* perm = nullptr;
-    hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->cfg.sort_bits, h->ws, &perm, st, d_sorted_points);
+    hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->cfg.sort_bits, ws, &perm, st, d_sorted_points);
     if (e == hipSuccess) e = hipMemcpyAsync(d_order, perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "sort launch");
     return P2M_OK;
@@ -395,6 +500,64 @@ int32_t p2m_query_counters(p2m_handle h, const float* d_points, int64_t n, float
                         d_counters, false, stream);
 }
 
+int32_t p2m_query_touched(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
+                          int32_t* d_out_tri, float* d_out_closest, unsigned long long* d_counters,
+                          int64_t* h_items, void* stream)
+{
+    if (!d_counters || !h_items) return fail(P2M_ERR_INVALID_ARG, "null counters or item counts");
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    DeviceGuard dg(h->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t sizes[7] = {(int64_t)h->H.site_rec.size(), (int64_t)h->H.adj.size() / 4,
+                              (int64_t)h->H.list_tri.size(), (int64_t)h->H.list_tri.size(),
+                              (int64_t)h->H.seed.size(), (int64_t)h->H.n_triangles,
+                              (int64_t)h->H.bvh.size() / 8};
+    int64_t total = 0;
+    for (int64_t k : sizes) total += (k + 3) / 4 * 4;
+    void* flags = nullptr;
+    hipError_t e = hipMalloc(&flags, (size_t)std::max<int64_t>(total, 4));
+    if (e != hipSuccess) return fail(P2M_ERR_OOM, std::string("flag hipMalloc: ") + hipGetErrorString(e));
+    e = p2m::launch_fill_u32((uint32_t*)flags, 0u, total / 4, st);
+    p2m::Touch t{};
+    uint8_t* ptr[7];
+    {
+        uint8_t* p = (uint8_t*)flags;
+        for (int k = 0; k < 7; ++k) {
+            ptr[k] = p;
+            p += (sizes[k] + 3) / 4 * 4;
+        }
+    }
+    t.site = ptr[0];
+    t.adj = ptr[1];
+    t.sph = ptr[2];
+    t.rec = ptr[3];
+    t.seed = ptr[4];
+    t.tri = ptr[5];
+    t.bvh = ptr[6];
+    int32_t rc = P2M_OK;
+    if (e != hipSuccess) rc = hip_fail(e, "flag clear");
+    if (rc == P2M_OK)
+        rc = query_common(h, d_points, n, d_out_dist, d_out_tri, d_out_closest, nullptr, nullptr, nullptr,
+                          d_counters, false, stream, &t);
+    std::vector<uint8_t> host((size_t)std::max<int64_t>(total, 4));
+    if (rc == P2M_OK) {
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipMemcpy(host.data(), flags, (size_t)total, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = hip_fail(e, "flag copy");
+    }
+    (void)hipFree(flags);
+    if (rc != P2M_OK) return rc;
+    size_t off = 0;
+    for (int k = 0; k < 7; ++k) {
+        int64_t c = 0;
+        for (int64_t i = 0; i < sizes[k]; ++i) c += host[off + (size_t)i] != 0;
+        h_items[k] = c;
+        off += (size_t)((sizes[k] + 3) / 4 * 4);
+    }
+    return P2M_OK;
+}
+
 int32_t p2m_query_fused(p2m_handle h, const float* d_points, int64_t n, const float* d_grad_dist,
                         float* d_out_dist, int32_t* d_out_tri, float* d_out_closest, float* d_grad_points,
                         float* d_grad_vertices, void* stream)
@@ -407,9 +570,9 @@ int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n, const
                            const float* d_closest, const float* d_dist, const float* d_grad_dist,
                            float* d_grad_points, float* d_grad_vertices, void* stream)
 {
-    (void)d_closest;
-    (void)d_dist;
     if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if ((d_closest == nullptr) != (d_dist == nullptr))
+        return fail(P2M_ERR_INVALID_ARG, "pass both the closest points and the distances, or neither");
     if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
     if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
     if (n == 0) return P2M_OK;
@@ -420,14 +583,16 @@ int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n, const
     // Visiting the points in spatial order lets a workgroup combine the
     // vertex gradients of neighbouring points before the global atomics.
     const int32_t* order = nullptr;
+    std::lock_guard<std::recursive_mutex> lk(h->mu);
     if (h->cfg.reorder && d_grad_vertices) {
-        int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st);
+        void* ws = nullptr;
+        int32_t rc = h->ensure_ws(p2m::reorder_workspace_bytes(n, h->cfg.sort_bits), st, &ws);
         if (rc != P2M_OK) return rc;
-        hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->cfg.sort_bits, h->ws, &order, st);
+        hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->cfg.sort_bits, ws, &order, st);
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
     }
-    hipError_t e = p2m::launch_backward(h->dm, d_points, n, order, d_tri, d_grad_dist, d_grad_points,
-                                        d_grad_vertices, h->cfg.block_size, st);
+    hipError_t e = p2m::launch_backward(h->dm, d_points, n, order, d_tri, d_closest, d_dist, d_grad_dist,
+                                        d_grad_points, d_grad_vertices, h->cfg.block_size, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return P2M_OK;
 }
@@ -443,8 +608,8 @@ int32_t p2m_query_backward_ordered(p2m_handle h, const float* d_points, const in
     if (!d_points || !d_tri || !d_grad_dist) return fail(P2M_ERR_INVALID_ARG, "null points, triangles or gradient");
     if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
     DeviceGuard dg(h->device);
-    hipError_t e = p2m::launch_backward(h->dm, d_points, n, d_order, d_tri, d_grad_dist, d_grad_points,
-                                        d_grad_vertices, h->cfg.block_size, (hipStream_t)stream);
+    hipError_t e = p2m::launch_backward(h->dm, d_points, n, d_order, d_tri, nullptr, nullptr, d_grad_dist,
+                                        d_grad_points, d_grad_vertices, h->cfg.block_size, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return P2M_OK;
 }

@@ -11,8 +11,9 @@ namespace p2m {
 struct DevMesh {
     const float4* site_rec;  // 2 per site: (x, y, z, 0), int4 (adj begin, end, list begin, end)
     const float4* adj;       // neighbour xyz + id bits
-    const float4* list_rec;  // 4 per list entry: (c, r), (a, ell), (e1, e1.e2), (e2, caller triangle id bits);
-                             // the scan recomputes a lower bound of ell from (c, r)
+    const float4* list_sph;  // 1 per list entry: bounding sphere (c, r); the scan recomputes a lower
+                             // bound of ell from it
+    const float4* list_rec;  // 3 per list entry, same index: (a, ell), (e1, e1.e2), (e2, caller triangle id bits)
     const float4* tri_rec;   // 3 per slot: (a, |e1|^2), (e1, e1.e2), (e2, |e2|^2)
     const int32_t* tri_user; // slot -> caller triangle id
     const int4* tri_vid;     // caller triangle id -> caller vertex ids
@@ -29,7 +30,25 @@ struct DevMesh {
 };
 
 // Counter slots of the instrumented forward.
-enum { CTR_WALK_STEPS = 0, CTR_ADJ_READ, CTR_LIST_READ, CTR_EXACT, CTR_FALLBACK, CTR_LIST_LEN, CTR_N };
+// CTR_WALK_CAP counts walks stopped at the step cap (answered by the exact
+// BVH fallback, so also counted in CTR_FALLBACK).
+enum { CTR_WALK_STEPS = 0, CTR_ADJ_READ, CTR_LIST_READ, CTR_EXACT, CTR_FALLBACK, CTR_LIST_LEN, CTR_WALK_CAP, CTR_N };
+
+// Instrumented forward only: one flag per item of each structure array,
+// set to 1 when a load touches the item, so that the distinct bytes one
+// launch reads can be counted (each array zeroed by the caller; null =
+// not recorded).  Items: site records (32 B), adjacency entries (16 B), list
+// spheres (16 B), list records (48 B), seed cells (4 B), triangle records
+// of the fallback (48 B), fallback BVH nodes (32 B).
+struct Touch {
+    uint8_t* site;
+    uint8_t* adj;
+    uint8_t* sph;
+    uint8_t* rec;
+    uint8_t* seed;
+    uint8_t* tri;
+    uint8_t* bvh;
+};
 
 struct FwdArgs {
     const float* q;          // n x 3: caller order, or visiting order when q_sorted
@@ -43,6 +62,7 @@ struct FwdArgs {
     float* grad_q;           // fused only, nullable
     float* grad_v;           // fused only, nullable
     unsigned long long* ctr; // counters only
+    Touch touch;             // counters only: distinct items read (see Touch)
     int32_t xcds;            // blocks are spread over this many XCD groups (see launch_forward)
     int32_t acc_slots;       // fused: LDS hash slots for vertex gradients (set by launch_forward)
 };
@@ -71,10 +91,13 @@ hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int
                         hipStream_t st);
 hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fused, bool counters,
                           hipStream_t st);
-// order (nullable): visit point order[j] at thread j.
+// order (nullable): visit point order[j] at thread j.  closest and dist
+// (nullable, both or neither): the forward's outputs, from which dL/dq is
+// formed; without them, and for the barycentrics dL/dV needs, the closest
+// point is recomputed from the triangle.
 hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* order,
-                           const int32_t* tri, const float* g, float* grad_q, float* grad_v, int block,
-                           hipStream_t st);
+                           const int32_t* tri, const float* closest, const float* dist, const float* g,
+                           float* grad_q, float* grad_v, int block, hipStream_t st);
 // Radix sort of queries by the Morton code of their cell in a 2^k grid
 // over the seed-grid box (k from n when bits = 0).  ws must hold
 // reorder_workspace_bytes(n) bytes; writes the order to *perm_out.
@@ -91,5 +114,9 @@ const int32_t* reorder_perm_location(void* ws, int64_t n, int bits);
 int reduce_blocks(int64_t n);
 hipError_t launch_reduce_dist(const float* d, int64_t n, double* part, double* out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// Combines two point-set reductions (5 doubles each, as launch_reduce_dist
+// leaves them: A's points against B, B's points against A) into the six
+// mesh-distance values of p2m_mesh_distance.
+hipError_t launch_mesh_distance_combine(const double* ab, const double* ba, double* out, hipStream_t st);
 
 }  // namespace p2m

@@ -158,15 +158,22 @@ __device__ __noinline__ int best_neighbour_f64(const DevMesh& m, const float3 q,
 // is taken only on a certified improvement, and when no neighbour is
 // certified better but one lies within the bound the site's neighbours are
 // re-evaluated in FP64.  The walk therefore stops exactly where an FP64 walk
-// would (a local, hence global, minimum on the Delaunay graph).
+// would (a local, hence global, minimum on the Delaunay graph).  A walk
+// that has not stopped after kWalkCap steps (not possible on a valid
+// Delaunay graph) returns -1 and is counted: the caller then answers the
+// query by the exact BVH search.
 template <bool kCtr>
 __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned long long& steps,
-                                      unsigned long long& adj_read, float4& sp_out, int4& rg_out)
+                                      unsigned long long& adj_read, unsigned long long& capped,
+                                      const Touch& tch, float4& sp_out, int4& rg_out)
 {
-    int s = m.seed[seed_cell(m, q)];
+    const int cell = seed_cell(m, q);
+    int s = m.seed[cell];
+    if (kCtr && tch.seed) tch.seed[cell] = 1;
     for (int it = 0; it < kWalkCap; ++it) {
         const float4 sp = m.site_rec[2 * s];
         const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        if (kCtr && tch.site) tch.site[s] = 1;
         sp_out = sp;
         rg_out = rg;
         const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
@@ -178,6 +185,8 @@ __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned
             float4 a[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) a[k] = m.adj[min(k0 + k, rg.y - 1)];
+            if (kCtr && tch.adj)
+                for (int k = 0; k < 4; ++k) tch.adj[min(k0 + k, rg.y - 1)] = 1;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const float dx = a[k].x - sp.x, dy = a[k].y - sp.y, dz = a[k].z - sp.z;
@@ -201,10 +210,8 @@ __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned
         if (nxt < 0) return s;
         s = nxt;
     }
-    // walk cap reached (not on a valid Delaunay graph): s's record
-    sp_out = m.site_rec[2 * s];
-    rg_out = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
-    return s;
+    if (kCtr) capped += 1;
+    return -1;
 }
 
 // Cell Locate in the octree decomposition: descend from the root to the leaf
@@ -235,6 +242,11 @@ struct Best {
     float v, w;
 };
 
+// Counts of one query for the instrumented forward.
+struct QueryCounts {
+    unsigned long long steps = 0, adj_read = 0, list_read = 0, exact = 0, list_len = 0, capped = 0;
+};
+
 // List Search over the located site's interception list.  Entries are
 // fetched kChunk at a time (all loads issued before any is used) so that
 // the scan keeps several requests in flight despite its data-dependent exit.
@@ -245,8 +257,7 @@ constexpr int kChunk = 4;
 // entry (else -1).
 template <bool kCtr>
 __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, const float4 sp, const int4 rg,
-                                            const int budget, int* resume, unsigned long long& list_read,
-                                            unsigned long long& exact, unsigned long long& list_len)
+                                            const int budget, int* resume, QueryCounts& n, const Touch& tch)
 {
     const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
     // |q - s| rounded up so that the early-exit bound stays conservative
@@ -261,13 +272,14 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
             stop = e;
             break;
         }
-        // the spheres (c, r) of kChunk entries; the rest of an entry (a, e1,
-        // e2) shares their cache line and is read for an exact test only
+        // the spheres (c, r) of kChunk entries, from the dense sphere array;
+        // an entry's record (a, e1, e2) is read for an exact test only
         float4 c[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const int idx = min(e + k, rg.w - 1);
-            c[k] = m.list_rec[4 * (int64_t)idx];
+            c[k] = m.list_sph[idx];
+            if (kCtr && tch.sph) tch.sph[idx] = 1;
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
@@ -292,11 +304,12 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
             const float lim = dmin + c[k].w;
             if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) continue;
             const int64_t idx = e + k;
-            const float4 f1 = m.list_rec[4 * idx + 1], f2 = m.list_rec[4 * idx + 2], f3 = m.list_rec[4 * idx + 3];
+            const float4 f1 = m.list_rec[3 * idx], f2 = m.list_rec[3 * idx + 1], f3 = m.list_rec[3 * idx + 2];
+            if (kCtr && tch.rec) tch.rec[idx] = 1;
             float v, w;
             const float d2 = closest_point(q, make_float3(f1.x, f1.y, f1.z), make_float3(f2.x, f2.y, f2.z),
                                            make_float3(f3.x, f3.y, f3.z), f2.w, v, w);
-            if (kCtr) exact += 1;
+            if (kCtr) n.exact += 1;
             if (d2 < b.d2) {
                 b.d2 = d2;
                 b.idx = (int)idx;
@@ -307,8 +320,8 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
         }
     }
     if (kCtr) {
-        list_read += (unsigned long long)(stop - rg.z);
-        list_len += (unsigned long long)(rg.w - rg.z);
+        n.list_read += (unsigned long long)(stop - rg.z);
+        n.list_len += (unsigned long long)(rg.w - rg.z);
     }
     return b;
 }
@@ -353,7 +366,7 @@ __device__ __forceinline__ float wave_min(float x)
 template <bool kCtr>
 __device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, const int s, const int from,
                                               const float dmin0, unsigned long long& list_read,
-                                              unsigned long long& exact)
+                                              unsigned long long& exact, const Touch tch)
 {
     const int lane = threadIdx.x & 63;
     const float4 sp = m.site_rec[2 * s];
@@ -368,8 +381,12 @@ __device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, 
 #pragma unroll
         for (int k = 0; k < kWaveChunk; ++k) {
             const int idx = min(base + 64 * k + lane, rg.w - 1);
-            c[k] = m.list_rec[4 * (int64_t)idx];
-            a[k] = m.list_rec[4 * (int64_t)idx + 1];
+            c[k] = m.list_sph[idx];
+            a[k] = m.list_rec[3 * (int64_t)idx];
+            if (kCtr && tch.sph) {
+                tch.sph[idx] = 1;
+                tch.rec[idx] = 1;
+            }
         }
         float dl = fminf(dmin, sqrtf(b.d2));
 #pragma unroll
@@ -380,7 +397,7 @@ __device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, 
                 const float dx = q.x - c[k].x, dy = q.y - c[k].y, dz = q.z - c[k].z;
                 const float lim = dl + c[k].w;
                 if (dx * dx + dy * dy + dz * dz < lim * lim * 1.000001f) {
-                    const float4 f2 = m.list_rec[4 * (int64_t)e + 2], f3 = m.list_rec[4 * (int64_t)e + 3];
+                    const float4 f2 = m.list_rec[3 * (int64_t)e + 1], f3 = m.list_rec[3 * (int64_t)e + 2];
                     float v, w;
                     const float d2 = closest_point(q, make_float3(a[k].x, a[k].y, a[k].z),
                                                    make_float3(f2.x, f2.y, f2.z), make_float3(f3.x, f3.y, f3.z),
@@ -396,7 +413,7 @@ __device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, 
         }
         dmin = wave_min(dl);
         const int last = min(base + 64 * kWaveChunk, rg.w) - 1;
-        if (m.list_rec[4 * (int64_t)last + 1].w - dqs >= dmin) {
+        if (m.list_rec[3 * (int64_t)last].w - dqs >= dmin) {
             end = last + 1;
             break;
         }
@@ -405,8 +422,10 @@ __device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, 
     return wave_argmin(b);
 }
 
-// Exact branch-and-bound over the triangle BVH (points outside the domain box).
-__device__ Best bvh_search(const DevMesh& m, const float3 q)
+// Exact branch-and-bound over the triangle BVH (points outside the domain
+// box, and walks stopped at the step cap).
+template <bool kCtr>
+__device__ Best bvh_search(const DevMesh& m, const float3 q, const Touch tch)
 {
     Best b{kInf, -1, 0.f, 0.f};
     int stack[64];
@@ -415,6 +434,7 @@ __device__ Best bvh_search(const DevMesh& m, const float3 q)
     while (sp > 0) {
         const int ni = stack[--sp];
         const float4 lo = m.bvh[2 * ni], hi = m.bvh[2 * ni + 1];
+        if (kCtr && tch.bvh) tch.bvh[ni] = 1;
         const float bx = fmaxf(fmaxf(lo.x - q.x, q.x - hi.x), 0.f);
         const float by = fmaxf(fmaxf(lo.y - q.y, q.y - hi.y), 0.f);
         const float bz = fmaxf(fmaxf(lo.z - q.z, q.z - hi.z), 0.f);
@@ -423,6 +443,7 @@ __device__ Best bvh_search(const DevMesh& m, const float3 q)
         if (c < 0) {
             for (int slot = a; slot < a - c; ++slot) {
                 const float4* r = m.tri_rec + 3 * (int64_t)slot;
+                if (kCtr && tch.tri) tch.tri[slot] = 1;
                 float v, w;
                 const float d2 = closest_point_rec(q, r, v, w);
                 if (d2 < b.d2) { b.d2 = d2; b.idx = -slot - 2; b.v = v; b.w = w; }
@@ -543,11 +564,6 @@ __device__ __forceinline__ void add_vertex_grads(const DevMesh& m, const Acc& ac
     }
 }
 
-// Counts of one query for the instrumented forward.
-struct QueryCounts {
-    unsigned long long steps = 0, adj_read = 0, list_read = 0, exact = 0, list_len = 0;
-};
-
 // The rest of one query after its lane's part of the list scan: lists left
 // unfinished (resume >= 0) are completed by the wavefront, then fallback,
 // outputs and, when fused, the gradient.  q is the point (finite tells
@@ -563,7 +579,7 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
                                              float* __restrict__ dist, int32_t* __restrict__ tri,
                                              float* __restrict__ closest, const float* __restrict__ gdist,
                                              float* __restrict__ grad_q, const Acc& acc,
-                                             unsigned long long* __restrict__ ctr, QueryCounts n)
+                                             unsigned long long* __restrict__ ctr, QueryCounts n, const Touch tch)
 {
     unsigned long long steps = n.steps, adj_read = n.adj_read, list_read = n.list_read, exact = n.exact,
                        list_len = n.list_len, fb = 0;
@@ -577,7 +593,7 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
         const int from = __builtin_amdgcn_readlane(resume, src);
         const float d0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sqrtf(b.d2)), src));
         unsigned long long lr = 0, ex = 0;
-        const Best r = list_search_wave<kCtr>(m, qs, ss, from, d0, lr, ex);
+        const Best r = list_search_wave<kCtr>(m, qs, ss, from, d0, lr, ex, tch);
         if ((int)(threadIdx.x & 63) == src) {
             // the lane's own result holds earlier entries and wins ties
             if (r.d2 < b.d2) b = r;
@@ -589,7 +605,7 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
     // lane goes on
     if (!kFused && !valid) return;
     if (valid && finite && b.idx == -1) {
-        b = bvh_search(m, q);
+        b = bvh_search<kCtr>(m, q, tch);
         fb = 1;
     }
     if (kCtr && valid) {
@@ -599,6 +615,7 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
         atomicAdd(&ctr[CTR_EXACT], exact);
         atomicAdd(&ctr[CTR_FALLBACK], fb);
         atomicAdd(&ctr[CTR_LIST_LEN], list_len);
+        atomicAdd(&ctr[CTR_WALK_CAP], n.capped);
     }
     int gtri = -1;        // fused: this lane's triangle for dL/dV, or -1
     float gc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -622,10 +639,10 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
         float4 r0, r1, r2;
         int user;
         if (b.idx >= 0) {
-            const float4* L = m.list_rec + 4 * (int64_t)b.idx;
-            r0 = L[1];
-            r1 = L[2];
-            r2 = L[3];
+            const float4* L = m.list_rec + 3 * (int64_t)b.idx;
+            r0 = L[0];
+            r1 = L[1];
+            r2 = L[2];
             user = __float_as_int(r2.w);
         } else {
             const int slot = -b.idx - 2;
@@ -696,17 +713,18 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
         // has just read it
         float4 sp;
         int4 rg;
+        const Touch none{};
         if (m.oct) {
             s = octree_locate(m, q, n.steps);
             sp = m.site_rec[2 * s];
             rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
         } else {
-            s = locate<kCtr>(m, q, n.steps, n.adj_read, sp, rg);
+            s = locate<kCtr>(m, q, n.steps, n.adj_read, n.capped, none, sp, rg);
         }
-        b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n.list_read, n.exact, n.list_len);
+        if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n, none);
     }
     finish_query<kFused, kCtr>(m, valid, q, finite, s, b, resume, i, dist, tri, closest, gdist, grad_q, acc, ctr,
-                               n);
+                               n, Touch{});
 }
 
 // Regroups a workgroup's queries by located site, so that lanes holding
@@ -718,14 +736,25 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
 // 255): a workgroup's few dozen sites rarely share a key, and a shared key
 // only interleaves two sites.  The ranking is stable (ballots over the key
 // bits rank a wavefront's lanes, per-wavefront counts in LDS order the
-// wavefronts), so the assignment is deterministic.  smem holds nw * 256
-// counts, zeroed by the caller before a barrier, then 5 words per thread.
-// Every thread of the workgroup must call it.
-__device__ __forceinline__ void regroup_by_site(int* smem, const int nw, float3& q, int64_t& i, int& s)
+// wavefronts), so the assignment is deterministic.
+//
+// `join` (uniform over the wavefront) says whether the wavefront takes
+// part: the queries of the joining wavefronts are regrouped over the slots
+// of those wavefronts only, and the others keep their own queries.  (A
+// wavefront holding a list longer than one lane's scan budget stays out:
+// it completes such lists one after the other, and gathering the lanes of
+// a long-list site into one wavefront would queue all their scans there.)
+//
+// smem holds nw * 256 counts, zeroed by the caller before a barrier, then
+// 5 words per thread, then nw flags.  Every thread of the workgroup must
+// call it.
+__device__ __forceinline__ void regroup_by_site(int* smem, const int nw, const bool join, float3& q, int64_t& i,
+                                                int& s)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int* wc = smem;                 // [nw][256]: counts, then starts
-    int* slot = smem + nw * 256;    // [blockDim][5]: x, y, z, i, s
+    int* wc = smem;                             // [nw][256]: counts, then starts
+    int* slot = smem + nw * 256;                // [blockDim][5]: x, y, z, i, s
+    int* part = slot + 5 * (int)blockDim.x;     // [nw]: the wavefront joins
     const uint32_t d = s >= 0 ? ((uint32_t)s & 255u) : 255u;
     uint64_t peers = ~0ull;
 #pragma unroll
@@ -736,7 +765,8 @@ __device__ __forceinline__ void regroup_by_site(int* smem, const int nw, float3&
     }
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int rank = __popcll(peers & below);
-    if (rank == 0) wc[wid * 256 + (int)d] = __popcll(peers);
+    if (lane == 0) part[wid] = join ? 1 : 0;
+    if (join && rank == 0) wc[wid * 256 + (int)d] = __popcll(peers);
     __syncthreads();
     if (wid == 0) {
         // lane l holds keys 4l..4l+3: totals, exclusive scan, per-wavefront starts
@@ -764,21 +794,34 @@ __device__ __forceinline__ void regroup_by_site(int* smem, const int nw, float3&
         }
     }
     __syncthreads();
-    const int pos = wc[wid * 256 + (int)d] + rank;
-    slot[5 * pos] = __float_as_int(q.x);
-    slot[5 * pos + 1] = __float_as_int(q.y);
-    slot[5 * pos + 2] = __float_as_int(q.z);
-    slot[5 * pos + 3] = (int)i;
-    slot[5 * pos + 4] = s;
+    int me = (int)threadIdx.x;
+    if (join) {
+        // position pos among the joining wavefronts' 64 * (number joining)
+        // slots: lane pos % 64 of the (pos / 64)-th joining wavefront
+        const int pos = wc[wid * 256 + (int)d] + rank;
+        int k = pos >> 6, w = 0;
+        for (; w < nw; ++w) {
+            if (part[w]) {
+                if (k == 0) break;
+                --k;
+            }
+        }
+        me = w * 64 + (pos & 63);
+    }
+    slot[5 * me] = __float_as_int(q.x);
+    slot[5 * me + 1] = __float_as_int(q.y);
+    slot[5 * me + 2] = __float_as_int(q.z);
+    slot[5 * me + 3] = (int)i;
+    slot[5 * me + 4] = s;
     __syncthreads();
-    const int me = (int)threadIdx.x;
-    q = make_float3(__int_as_float(slot[5 * me]), __int_as_float(slot[5 * me + 1]), __int_as_float(slot[5 * me + 2]));
-    i = slot[5 * me + 3];
-    s = slot[5 * me + 4];
+    const int t = (int)threadIdx.x;
+    q = make_float3(__int_as_float(slot[5 * t]), __int_as_float(slot[5 * t + 1]), __int_as_float(slot[5 * t + 2]));
+    i = slot[5 * t + 3];
+    s = slot[5 * t + 4];
 }
 
 // LDS of regroup_by_site for a workgroup of `block` threads, in ints.
-__host__ __device__ inline int regroup_lds_ints(int block) { return (block / 64) * 256 + block * 5; }
+__host__ __device__ inline int regroup_lds_ints(int block) { return (block / 64) * 257 + block * 5; }
 
 // Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
 // b mod x).  Remapping block b to logical block (b mod x) * per + b / x gives
@@ -818,39 +861,38 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
     float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
     int4 rg = make_int4(0, 0, 0, 0);
     if (finite && in_domain(m, q)) {
-        unsigned long long steps = 0, adj_read = 0;
+        unsigned long long steps = 0, adj_read = 0, capped = 0;
         if (m.oct) {
             s = octree_locate(m, q, steps);
             sp = m.site_rec[2 * s];
             rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
         } else {
-            s = locate<kCtr>(m, q, steps, adj_read, sp, rg);
+            s = locate<kCtr>(m, q, steps, adj_read, capped, a.touch, sp, rg);
         }
         if (kCtr) {
             atomicAdd(&a.ctr[CTR_WALK_STEPS], steps);
             atomicAdd(&a.ctr[CTR_ADJ_READ], adj_read);
+            atomicAdd(&a.ctr[CTR_WALK_CAP], capped);
         }
     }
-    // A workgroup holding a list longer than one lane's scan budget is left
-    // as it is: its wavefronts complete long lists one after the other, and
-    // gathering the lanes of such a site into one wavefront would queue all
-    // their scans there.
+    // Wavefronts holding a list longer than one lane's scan budget keep
+    // their queries (see regroup_by_site); the others regroup among
+    // themselves.
     int64_t i2 = valid ? i : -1;
-    if (!__syncthreads_or(s >= 0 && rg.w - rg.z > kSerialBudget)) {
-        regroup_by_site(rg_smem, nw, q, i2, s);
-        if (s >= 0) {
-            sp = m.site_rec[2 * s];
-            rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
-        }
+    const bool join = __ballot(s >= 0 && rg.w - rg.z > kSerialBudget) == 0ull;
+    regroup_by_site(rg_smem, nw, join, q, i2, s);
+    if (s >= 0) {
+        sp = m.site_rec[2 * s];
+        rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
     }
     const bool valid2 = i2 >= 0;
     const bool finite2 = valid2 && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
     QueryCounts n;
     Best b{kInf, -1, 0.f, 0.f};
     int resume = -1;
-    if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n.list_read, n.exact, n.list_len);
+    if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n, a.touch);
     finish_query<kFused, kCtr>(m, valid2, q, finite2, s, b, resume, valid2 ? i2 : 0, a.dist, a.tri, a.closest,
-                               a.grad_dist, a.grad_q, acc, a.ctr, n);
+                               a.grad_dist, a.grad_q, acc, a.ctr, n, a.touch);
     if (gv) {
         __syncthreads();
         acc.flush();
@@ -925,7 +967,9 @@ __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__
 
 __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float* __restrict__ qp, int64_t n,
                                                    const int32_t* __restrict__ order,
-                                                   const int32_t* __restrict__ tri, const float* __restrict__ gd,
+                                                   const int32_t* __restrict__ tri,
+                                                   const float* __restrict__ closest,
+                                                   const float* __restrict__ dist, const float* __restrict__ gd,
                                                    float* __restrict__ grad_q, float* __restrict__ grad_v,
                                                    int acc_slots, int tiles)
 {
@@ -952,17 +996,29 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
             const int tt = tri[i];
             float nx = 0.f, ny = 0.f, nz = 0.f, g = 0.f, v = 0.f, w = 0.f, d = 0.f;
             if (tt >= 0 && tt < m.n_tris) {
-                const int slot = m.tri_slot[tt];
                 const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
-                const float4* r = m.tri_rec + 3 * (int64_t)slot;
-                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-                d = sqrtf(closest_point_rec(q, r, v, w));
                 g = gd[i];
-                if (d > 0.f) {
-                    const float inv = 1.f / d;
-                    nx = (q.x - r0.x - v * r1.x - w * r2.x) * inv;
-                    ny = (q.y - r0.y - v * r1.y - w * r2.y) * inv;
-                    nz = (q.z - r0.z - v * r1.z - w * r2.z) * inv;
+                if (closest) {
+                    // (q - p) / d from the forward's outputs; the triangle is
+                    // read only for the barycentrics dL/dV needs
+                    d = dist[i];
+                    if (d > 0.f) {
+                        const float inv = 1.f / d;
+                        nx = (q.x - closest[3 * i]) * inv;
+                        ny = (q.y - closest[3 * i + 1]) * inv;
+                        nz = (q.z - closest[3 * i + 2]) * inv;
+                    }
+                    if (grad_v) (void)closest_point_rec(q, m.tri_rec + 3 * (int64_t)m.tri_slot[tt], v, w);
+                } else {
+                    const float4* r = m.tri_rec + 3 * (int64_t)m.tri_slot[tt];
+                    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+                    d = sqrtf(closest_point_rec(q, r, v, w));
+                    if (d > 0.f) {
+                        const float inv = 1.f / d;
+                        nx = (q.x - r0.x - v * r1.x - w * r2.x) * inv;
+                        ny = (q.y - r0.y - v * r1.y - w * r2.y) * inv;
+                        nz = (q.z - r0.z - v * r1.z - w * r2.z) * inv;
+                    }
                 }
             }
             if (grad_q) {
@@ -1315,9 +1371,10 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
 }
 
 hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* order,
-                           const int32_t* tri, const float* g, float* grad_q, float* grad_v, int block,
-                           hipStream_t st)
+                           const int32_t* tri, const float* closest, const float* dist, const float* g,
+                           float* grad_q, float* grad_v, int block, hipStream_t st)
 {
+    if ((closest == nullptr) != (dist == nullptr)) return hipErrorInvalidValue;
     if (n <= 0) return hipSuccess;
     const int slots = acc_slots_capped(kBwdSlotsPerThread * block);
     const size_t lds = grad_v ? acc_lds_bytes(slots) + 16 : 0;
@@ -1336,7 +1393,8 @@ hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const in
         }
     }
     const int64_t grid = (n_tiles + tiles - 1) / tiles;
-    bwd_kernel<<<(unsigned)grid, block, lds, st>>>(m, q, n, order, tri, g, grad_q, grad_v, slots, (int)tiles);
+    bwd_kernel<<<(unsigned)grid, block, lds, st>>>(m, q, n, order, tri, closest, dist, g, grad_q, grad_v, slots,
+                                                   (int)tiles);
     return hipGetLastError();
 }
 
@@ -1524,6 +1582,30 @@ hipError_t launch_reduce_dist(const float* d, int64_t n, double* part, double* o
     const int nb = reduce_blocks(n);
     reduce_dist_kernel<<<nb, kRedBlock, 0, st>>>(d, n, part);
     reduce_final_kernel<<<1, kRedBlock, 0, st>>>(part, nb, out);
+    return hipGetLastError();
+}
+
+// The six values of p2m_mesh_distance from the two one-sided reductions
+// (max, argmax, sum, sum of squares, count): one-sided Hausdorff A to B and
+// B to A, the symmetric one, the Chamfer sums of means of d and of d^2 (a
+// side without points contributes 0), and the number of points counted.
+__global__ void mesh_distance_combine_kernel(const double* __restrict__ ab, const double* __restrict__ ba,
+                                             double* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    const double hab = ab[0], hba = ba[0];
+    out[0] = hab;
+    out[1] = hba;
+    out[2] = hab > hba ? hab : hba;
+    const double na = ab[4], nb = ba[4];
+    out[3] = (na > 0.0 ? ab[2] / na : 0.0) + (nb > 0.0 ? ba[2] / nb : 0.0);
+    out[4] = (na > 0.0 ? ab[3] / na : 0.0) + (nb > 0.0 ? ba[3] / nb : 0.0);
+    out[5] = na + nb;
+}
+
+hipError_t launch_mesh_distance_combine(const double* ab, const double* ba, double* out, hipStream_t st)
+{
+    mesh_distance_combine_kernel<<<1, 64, 0, st>>>(ab, ba, out);
     return hipGetLastError();
 }
 

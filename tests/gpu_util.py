@@ -17,12 +17,21 @@ def to_np(t):
     return t.detach().cpu().numpy()
 
 
+def exact_reference(V, F, Q, want_closest=True):
+    """The oracle's exact FP64 result for every point of ``Q``: the tier-B
+    branch-and-bound, bit-identical to the brute force (which its own tests
+    pin), fast enough for the full-size point sets.  ``(d, tri, closest)``."""
+    d, t, p, _ = oracle.distance_exact(V, F, Q, want_closest=want_closest)
+    return d, t, p
+
+
 def check_forward(V, F, Q, dist, tri, closest, D, d64=None, label=""):
     """Assert the acceptance rules; returns (max |dd|/D, p99.9 |dd|/D)."""
     tol = 1e-5 * D
     dist, tri, closest = np.asarray(dist), np.asarray(tri), np.asarray(closest)
     if d64 is None:
         d64, _, _, _ = oracle.distance(V, F, Q, want_closest=False)
+    assert len(dist) == len(Q) == len(d64)
     err = np.abs(dist.astype(np.float64) - d64)
     bad = np.nonzero(~(err <= tol))[0]
     assert len(bad) == 0, f"{label}: {len(bad)} distances off, worst {err[bad].max() if len(bad) else 0}, first {bad[:5]}"

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import gen
+import oracle
 
 from gpu_util import check_forward, to_np
 
@@ -105,6 +106,39 @@ def test_batched_fused_equals_plain(dev, c4_small):
             assert torch.equal(dist[s], d) and torch.equal(tri[s], t) and torch.equal(gq[s], gq_ref)
             err = torch.linalg.norm(gvs[i] - gv_ref) / max(torch.linalg.norm(gv_ref).item(), 1e-30)
             assert err <= 1e-5, (rep, i, err)
+
+
+def test_batched_fused_against_oracle_gradient(dev, c4_small):
+    """The batched fused form's dL/dq and every mesh's dL/dV against the
+    FP64 envelope-theorem gradient of the oracle (at the GPU's triangles;
+    their distances are checked against the oracle first), on the first
+    5,000 points of each mesh."""
+    cfg, meshes = c4_small
+    sub = [dict(c, Q=c["Q"][:5000]) for c in cfg]
+    Q, off = concat_points(sub)
+    n = len(Q)
+    rng = np.random.default_rng(32)
+    gnp = rng.normal(size=n).astype(np.float32)
+    q = torch.from_numpy(Q).cuda()
+    g = torch.from_numpy(gnp).cuda()
+    dist = torch.empty(n, device="cuda")
+    tri = torch.empty(n, dtype=torch.int32, device="cuda")
+    cl = torch.empty((n, 3), device="cuda")
+    gq = torch.empty((n, 3), device="cuda")
+    gvs = [torch.zeros((len(m.V), 3), device="cuda") for m in meshes]
+    b = dev.Batch(meshes, [len(c["Q"]) for c in sub], autotune=False)
+    b.bind(q, dist, tri, cl, grad_dist=g, grad_points=gq, grad_vertices=gvs)
+    b.launch()
+    torch.cuda.synchronize()
+    dn, tn, cn, gqn = to_np(dist), to_np(tri), to_np(cl), to_np(gq)
+    for i, c in enumerate(sub):
+        s = slice(off[i], off[i + 1])
+        V, F = c["V"], c["F"]
+        check_forward(V, F, Q[s], dn[s], tn[s], cn[s], c["D"], label=c["name"])
+        dq64, dV64 = oracle.gradient(V, F, Q[s], tn[s], gnp[s])
+        eq = np.linalg.norm(gqn[s] - dq64) / max(np.linalg.norm(dq64), 1e-30)
+        ev = np.linalg.norm(to_np(gvs[i]) - dV64) / max(np.linalg.norm(dV64), 1e-30)
+        assert eq <= 1e-3 and ev <= 1e-3, (c["name"], eq, ev)
 
 
 def test_batched_plan_prefix_full_meshes(dev):

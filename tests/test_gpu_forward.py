@@ -8,7 +8,7 @@ import pytest
 import gen
 import oracle
 
-from gpu_util import check_forward, to_np
+from gpu_util import check_forward, exact_reference, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -117,7 +117,7 @@ def test_counters_match_plain_forward(dev, c0):
     d1, t1, c1, ctr = dev.query_counters(m, q)
     assert torch.equal(d0, d1) and torch.equal(t0, t1) and torch.equal(c0_, c1)
     assert ctr["walk_steps"] >= len(c["Q"]) and ctr["exact_tests"] >= len(c["Q"])
-    assert ctr["list_read"] <= ctr["list_len"] and ctr["fallback"] == 0
+    assert ctr["list_read"] <= ctr["list_len"] and ctr["fallback"] == 0 and ctr["walk_capped"] == 0
 
 
 def test_small_and_degenerate_meshes(dev):
@@ -153,36 +153,26 @@ def test_c1_subset(dev, c1):
     print("C1 max|dd|/D, p99.9:", check_forward(c["V"], c["F"], c["Q"], d, t, cl, c["D"], label="C1"))
 
 
-def check_full_size(dev, c, m, n_sample, seed):
+def check_full_size(dev, c, m):
     """The whole workload through p2m_query (the benchmark's launch
-    configuration); the oracle checks a seeded sample of outputs one by one,
-    invariants check all of them."""
+    configuration), run twice (deterministic), and every output checked
+    against the oracle's exact result under the acceptance rules."""
     q = torch.from_numpy(c["Q"]).cuda()
     d, t, cl = dev.query(m, q)
     d2, t2, cl2 = dev.query(m, q)
     torch.cuda.synchronize()
     assert torch.equal(d, d2) and torch.equal(t, t2) and torch.equal(cl, cl2)   # deterministic
     d, t, cl = to_np(d), to_np(t), to_np(cl)
-    n = len(c["Q"])
-    rng = np.random.default_rng(seed)
-    h = n_sample // 2
-    idx = np.concatenate([rng.choice(n // 2, h, replace=False), n // 2 + rng.choice(n - n // 2, h, replace=False)])
-    res = check_forward(c["V"], c["F"], c["Q"][idx], d[idx], t[idx], cl[idx], c["D"], label=c["name"])
-    tol = 1e-5 * c["D"]
-    assert t.min() >= 0 and t.max() < len(c["F"])
-    on = oracle.distance_to_triangles64(c["V"], c["F"], cl.astype(np.float64), t)
-    assert on.max() <= tol                                  # closest point on its triangle
-    dq = np.linalg.norm(c["Q"].astype(np.float64) - cl, axis=1)
-    assert np.abs(dq - d).max() <= tol                      # |q - p| = d
-    return res
+    d64, _, _ = exact_reference(c["V"], c["F"], c["Q"], want_closest=False)
+    return check_forward(c["V"], c["F"], c["Q"], d, t, cl, c["D"], d64=d64, label=c["name"])
 
 
-def test_c1_full_size_sampled(dev):
+def test_c1_full_size(dev):
     """C1 at its full size: 512 x 128 cylinder + cone (263,168 triangles),
-    1M uniform + 1M near-surface points."""
+    1M uniform + 1M near-surface points, every output against the oracle."""
     c = gen.config_c1()
     m = dev.Mesh(c["V"], c["F"])
-    print("C1 full sample max|dd|/D, p99.9:", check_full_size(dev, c, m, 3000, 2025))
+    print("C1 full max|dd|/D, p99.9:", check_full_size(dev, c, m))
 
 
 @pytest.fixture(scope="module")
@@ -191,10 +181,100 @@ def c2(dev):
     return c, dev.Mesh(c["V"], c["F"])
 
 
-def test_c2_full_size_sampled(dev, c2):
-    """Full C2 workload (10M points) in the benchmark's launch configuration."""
+def test_c2_full_size(dev, c2):
+    """Full C2 workload (10M points) in the benchmark's launch configuration,
+    every output against the oracle."""
     c, m = c2
-    print("C2 sample max|dd|/D, p99.9:", check_full_size(dev, c, m, 3000, 2024))
+    print("C2 full max|dd|/D, p99.9:", check_full_size(dev, c, m))
+
+
+def test_c2_no_walk_reaches_the_step_cap(dev, c2):
+    """The instrumented forward on 1M points of C2: no walk stops at the step
+    cap, nothing falls back, and the outputs equal the plain forward's."""
+    c, m = c2
+    q = torch.from_numpy(c["Q"][::10].copy()).cuda()
+    d0, t0, c0_ = dev.query(m, q)
+    d1, t1, c1_, ctr = dev.query_counters(m, q)
+    assert torch.equal(d0, d1) and torch.equal(t0, t1) and torch.equal(c0_, c1_)
+    assert ctr["walk_capped"] == 0 and ctr["fallback"] == 0
+
+
+def test_c2_touched_items(dev, c2):
+    """p2m_query_touched: same outputs as the plain forward; the distinct
+    items it reports are within the arrays' sizes and at least what the
+    counters imply (every located site, one seed cell per point cell)."""
+    c, m = c2
+    q = torch.from_numpy(c["Q"][:500_000].copy()).cuda()
+    d0, t0, c0_ = dev.query(m, q)
+    d1, t1, c1_, ctr, items = dev.query_touched(m, q)
+    assert torch.equal(d0, d1) and torch.equal(t0, t1) and torch.equal(c0_, c1_)
+    st = m.stats()
+    assert 0 < items["site_rec"][0] <= st["n_sites"]
+    assert 0 < items["adjacency"][0] <= st["adj_nnz"]
+    assert 0 < items["list_sphere"][0] <= st["list_nnz"]
+    assert 0 < items["list_record"][0] <= items["list_sphere"][0]
+    assert items["list_sphere"][0] <= ctr["list_read"] + 3 * ctr["walk_steps"]     # at most what was read
+    assert items["fallback_triangle"][0] == 0 and items["fallback_bvh_node"][0] == 0
+
+
+@pytest.mark.parametrize("name", ["C0", "icosphere-5"])
+def test_without_augmentation(dev, name):
+    """augment = 0 (vertex sites only, the ablation of the paper's Tab. 4):
+    on the UV sphere and the icosphere every vertex cell reaches the centre,
+    so lists hold about every triangle and the wavefront completes long
+    lists on nearly every query.  Every output against the oracle."""
+    if name == "C0":
+        c = gen.config_c0()
+        V, F, Q, D = c["V"], c["F"], c["Q"], c["D"]
+    else:
+        V, F = gen.icosphere(5)
+        D = float(np.linalg.norm(V.max(0) - V.min(0)))
+        rng = np.random.default_rng(61)
+        lo, hi = gen.scaled_box(V, 1.2)
+        Q = np.concatenate([gen.uniform_box(rng, 20_000, lo, hi), gen.near_surface(rng, 20_000, V, F, 0.005 * D),
+                            gen.uniform_box(rng, 5_000, *gen.scaled_box(V, 10.0))]).astype(np.float32)
+    m = dev.Mesh(V, F, augment=0)
+    st = m.stats()
+    assert st["n_aux_sites"] == 0 and st["list_max"] > 0.5 * len(F)
+    d, t, cl = run(dev, m, Q)
+    d64, _, _ = exact_reference(V, F, Q, want_closest=False)
+    print(name, "augment=0 max|dd|/D, p99.9:", check_forward(V, F, Q, d, t, cl, D, d64=d64, label=name))
+    _, _, _, ctr = dev.query_counters(m, torch.from_numpy(Q).cuda())
+    assert ctr["walk_capped"] == 0
+
+
+def test_two_streams_one_handle(dev, c0):
+    """The handle is read-only after build: queries of different point sets
+    enqueued on two streams at once (each stream with its own scratch) give
+    the results of the same queries run one after the other."""
+    c, m = c0
+    rng = np.random.default_rng(71)
+    sets = [rng.uniform(-1.5, 1.5, (n, 3)).astype(np.float32) for n in (200_003, 150_001)]
+    qs = [torch.from_numpy(Q).cuda() for Q in sets]
+    ref = [dev.query(m, q) for q in qs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        outs = [None, None]
+        for k in (0, 1):
+            streams[k].wait_stream(torch.cuda.current_stream())
+        for k in (0, 1):
+            with torch.cuda.stream(streams[k]):
+                outs[k] = dev.query(m, qs[k], stream=streams[k])
+        # larger sets on the second round: the scratch regrows per stream
+        torch.cuda.synchronize()
+        for k in (0, 1):
+            for a, b in zip(ref[k], outs[k]):
+                assert torch.equal(a, b), (rep, k)
+    Q = rng.uniform(-1.5, 1.5, (400_000, 3)).astype(np.float32)
+    q = torch.from_numpy(Q).cuda()
+    r0 = dev.query(m, q)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(streams[1]):
+        r1 = dev.query(m, q, stream=streams[1])
+    torch.cuda.synchronize()
+    for a, b in zip(r0, r1):
+        assert torch.equal(a, b)
 
 
 def test_rejects_bad_counts_before_any_launch(dev):
@@ -213,4 +293,8 @@ def test_rejects_bad_counts_before_any_launch(dev):
         assert lib.p2m_point_set_distance(m.handle, p, n, p, None) == _lib.P2M_ERR_INVALID_ARG
         assert lib.p2m_sort_points(m.handle, p, n, p, None, None) == _lib.P2M_ERR_INVALID_ARG
         assert lib.p2m_query_backward(m.handle, p, n, p, None, None, p, None, None, None) == _lib.P2M_ERR_INVALID_ARG
+        assert lib.p2m_mesh_distance(m.handle, m.handle, p, n, None, 0, p, None) == _lib.P2M_ERR_INVALID_ARG
     assert lib.p2m_query(m.handle, p, 5, None, None, None, None) == _lib.P2M_ERR_INVALID_ARG   # null distance
+    # closest points without distances (or the reverse) for the backward
+    assert lib.p2m_query_backward(m.handle, p, 5, p, p, None, p, p, None, None) == _lib.P2M_ERR_INVALID_ARG
+    assert lib.p2m_mesh_distance(m.handle, m.handle, None, 5, None, 0, p, None) == _lib.P2M_ERR_INVALID_ARG

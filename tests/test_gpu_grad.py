@@ -7,7 +7,7 @@ import pytest
 import gen
 import oracle
 
-from gpu_util import to_np
+from gpu_util import check_forward, exact_reference, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -75,6 +75,48 @@ def test_c3_sample_against_oracle_gradient(dev, c3):
     assert np.all(rowq <= 1e-3 * np.maximum(np.linalg.norm(dq64, axis=1), 1e-3))
 
 
+def test_c3_full_size_against_oracle_gradient(dev, c3):
+    """All 4M points of C3: the forward against the oracle's exact result,
+    and the whole dL/dq (4M x 3) and dL/dV (163,842 x 3) against the FP64
+    envelope-theorem gradient taken at the oracle's own argmins.  Medial ties
+    (a different triangle with a different closest point, where the gradient
+    jumps) are masked with g = 0 in both runs."""
+    c, m = c3
+    V, F, D, Q = c["V"], c["F"], c["D"], c["Q"]
+    d64, t64, p64 = exact_reference(V, F, Q)
+    q = torch.from_numpy(Q).cuda()
+    d, t, cl = dev.query(m, q)
+    torch.cuda.synchronize()
+    d, t, cl = to_np(d), to_np(t), to_np(cl)
+    print("C3 forward max|dd|/D, p99.9:", check_forward(V, F, Q, d, t, cl, D, d64=d64, label="C3"))
+    tie = (t != t64) & (np.linalg.norm(cl - p64, axis=1) > 1e-5 * D)
+    assert tie.mean() < 1e-3, tie.mean()
+    g = c["G"].copy()
+    g[tie] = 0.0
+    gt = torch.from_numpy(g).cuda()
+    gv = torch.zeros((len(V), 3), dtype=torch.float32, device="cuda")
+    gq, gv = dev.query_backward(m, q, torch.from_numpy(t).cuda(), gt, grad_vertices=gv)
+    gv2 = torch.zeros_like(gv)
+    _, _, _, gq2 = dev.query_fused(m, q, gt, grad_vertices=gv2)
+    torch.cuda.synchronize()
+    dq64, dV64 = oracle.gradient(V, F, Q, t64, g)
+    for name, a, b in (("backward dL/dq", to_np(gq), dq64), ("backward dL/dV", to_np(gv), dV64),
+                       ("fused dL/dq", to_np(gq2), dq64), ("fused dL/dV", to_np(gv2), dV64)):
+        e = rel_err(a, b)
+        print(f"C3 {name}: norm-wise relative error {e:.3e}")
+        assert e <= 1e-3, (name, e)
+    # row by row against the FP64 gradient at the GPU's own triangles (at
+    # shared edges and vertices those are equally correct)
+    dq64g, dV64g = oracle.gradient(V, F, Q, t, g)
+    rms = np.sqrt(np.mean(np.sum(dV64g ** 2, axis=1)))
+    for a in (to_np(gv), to_np(gv2)):
+        row = np.linalg.norm(a - dV64g, axis=1)
+        assert np.all(row <= 1e-3 * np.maximum(np.linalg.norm(dV64g, axis=1), 1e-3 * rms))
+    for a in (to_np(gq), to_np(gq2)):
+        rowq = np.linalg.norm(a - dq64g, axis=1)
+        assert np.all(rowq <= 1e-3 * np.maximum(np.linalg.norm(dq64g, axis=1), 1e-3))
+
+
 def test_c3_full_size_invariants_and_fused(dev, c3):
     c, m = c3
     q = torch.from_numpy(c["Q"]).cuda()
@@ -99,6 +141,33 @@ def test_c3_full_size_invariants_and_fused(dev, c3):
     # translating mesh and points together leaves d unchanged
     s = gqn.astype(np.float64).sum(0) + to_np(gv).astype(np.float64).sum(0)
     assert np.linalg.norm(s) <= 1e-4 * np.abs(gqn).sum()
+
+
+def test_backward_from_forward_outputs(dev, c3):
+    """p2m_query_backward given the forward's closest points and distances
+    forms dL/dq from them (and reads the triangle only for dL/dV): the
+    result agrees with the recomputing backward to float32 rounding, and
+    dL/dV is the same up to the order of float32 additions."""
+    c, m = c3
+    q = torch.from_numpy(c["Q"][:1_000_000]).cuda()
+    g = torch.from_numpy(c["G"][:1_000_000]).cuda()
+    d, t, cl = dev.query(m, q)
+    gv0 = torch.zeros((len(m.V), 3), device="cuda")
+    gq0, gv0 = dev.query_backward(m, q, t, g, grad_vertices=gv0)
+    gv1 = torch.zeros_like(gv0)
+    gq1, gv1 = dev.query_backward(m, q, t, g, grad_vertices=gv1, closest=cl, dist=d)
+    gq2, _ = dev.query_backward(m, q, t, g, closest=cl, dist=d)
+    torch.cuda.synchronize()
+    assert torch.equal(gq1, gq2)
+    a, b = to_np(gq1).astype(np.float64), to_np(gq0).astype(np.float64)
+    # q - p formed from the rounded closest point instead of the residual:
+    # a few float32 roundings of the coordinates (~3e-7 here), relative to d
+    dd, gg = to_np(d), np.abs(to_np(g))
+    far = dd >= 1e-2
+    assert far.sum() > 100_000
+    assert np.all(np.linalg.norm(a - b, axis=1)[far] <= 1e-4 * gg[far] + 1e-12)
+    assert rel_err(a, b) <= 1e-4
+    assert rel_err(to_np(gv1), to_np(gv0)) <= 1e-5
 
 
 def region_key(V, F, Q, tri):

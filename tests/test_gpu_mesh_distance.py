@@ -83,6 +83,37 @@ def test_hausdorff_and_chamfer_helpers(dev):
     assert abs(dev.chamfer(ma, mb) - ch) <= 2 * tol
 
 
+def test_mesh_distance_call_against_oracle(dev):
+    """p2m_mesh_distance: both one-sided Hausdorff distances, the symmetric
+    one, the Chamfer distances (means of d and d^2) and the count, on the
+    default vertex sets and on caller point sets of different sizes, against
+    the oracle's one-sided reductions composed here; a mesh against itself
+    is 0."""
+    Va, Fa = gen.displaced_icosphere(4, np.random.default_rng(43))
+    Vb, Fb = gen.torus(0.9, 0.35, 80, 30)
+    ma, mb = dev.Mesh(Va, Fa), dev.Mesh(Vb, Fb)
+    tol = 1e-5 * 3.0
+    rng = np.random.default_rng(44)
+    sa = gen.near_surface(rng, 7001, Va, Fa, 0.0)
+    sb = np.concatenate([gen.near_surface(rng, 3000, Vb, Fb, 0.0), [[np.nan, 0, 0]]]).astype(np.float32)
+    for pa, pb in ((None, None), (sa, sb), (sa, None)):
+        ua = Va[np.unique(Fa)] if pa is None else pa
+        ub = Vb[np.unique(Fb)] if pb is None else pb
+        oab = oracle.point_set_distance(Vb, Fb, ua)
+        oba = oracle.point_set_distance(Va, Fa, ub)
+        r = dev.mesh_distance(ma, mb, None if pa is None else torch.from_numpy(pa).cuda(),
+                              None if pb is None else torch.from_numpy(pb).cuda())
+        assert r["count"] == oab["count"] + oba["count"]
+        assert abs(r["hausdorff_ab"] - oab["max"]) <= tol and abs(r["hausdorff_ba"] - oba["max"]) <= tol
+        assert r["hausdorff"] == max(r["hausdorff_ab"], r["hausdorff_ba"])
+        ch = oab["sum"] / oab["count"] + oba["sum"] / oba["count"]
+        ch2 = oab["sum_sq"] / oab["count"] + oba["sum_sq"] / oba["count"]
+        assert abs(r["chamfer"] - ch) <= 2 * tol
+        assert abs(r["chamfer_sq"] - ch2) <= 4 * tol * (oab["max"] + oba["max"] + tol)
+    r = dev.mesh_distance(ma, ma)
+    assert r["hausdorff"] <= 1e-6 and r["chamfer"] <= 1e-6
+
+
 def test_full_size_consistent_with_query(dev):
     """10M points on the 327,680-triangle mesh: the reduction equals the same
     reduction of p2m_query's distances."""
