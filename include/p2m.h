@@ -66,7 +66,15 @@ typedef struct {
                                   median) distinct sites have a Voronoi vertex in it; the
                                   median is over grid cells holding mesh vertices (256) */
     float dense_rel;           /* (8) */
-    int32_t ring_sites;        /* auxiliary sites on the enclosing sphere: 12 (icosahedron) */
+    int32_t ring_sites;        /* ring_layers = 0: sites on the one enclosing sphere of a dense
+                                  cluster (12, the icosahedron's directions); > 0: the fewest
+                                  sites of one ring (12) */
+    int32_t ring_layers;       /* > 0 (default 8): about a dense cluster at distance d from the
+                                  mesh, up to this many layers of auxiliary sites at radii d/2,
+                                  d/4, ... (down to tau), each about tau apart: rings normal to
+                                  the cluster's axis when its Voronoi vertices lie along a line
+                                  (cylinder, cone and torus cores), else spherical shells;
+                                  0: the one enclosing sphere of ring_sites sites */
     int32_t aux_list_mode;     /* 0: one conservative sphere per auxiliary site, Eq. (8);
                                   1: corner balls about the site's projection on the mesh
                                   (Eq. (3) with that reference point; a subset of mode 0) (1) */
@@ -110,6 +118,10 @@ typedef struct {
                            1 (default, measured faster on MI355X) = plain block order */
     int32_t sort_bits;  /* sort grid of 2^sort_bits cells per axis (1..8); 0 = automatic,
                            the finest grid with at most two cells per point */
+    int32_t stage;      /* 1 (default): each wavefront copies the bounding spheres of its
+                           located sites' lists into LDS with coalesced loads before the list
+                           scan (up to 256 per wavefront); 0: the scan gathers them from
+                           device memory.  Results are identical. */
 } p2m_query_config;
 
 void p2m_default_opts(p2m_build_opts* opts);
@@ -205,21 +217,19 @@ int32_t p2m_query_ordered(p2m_handle h, const float* d_points, const int32_t* d_
  *   dL/dq_i = g_i (q_i - p_i) / d_i;
  *   dL/dv_k += -g_i lambda_k (q_i - p_i) / d_i for the 3 vertices of tri_i,
  * with lambda the barycentrics of the closest point p_i; 0 when d_i = 0.
- *   d_tri:           the forward's triangle ids for the same points
- *   d_closest, d_dist: the forward's closest points and distances (device,
- *                    nullable: both or neither).  Given, dL/dq is formed
- *                    from them and the triangle is read only for the
- *                    barycentrics of dL/dV (so dL/dq alone reads no
- *                    triangle); NULL, the closest point is recomputed from
- *                    the triangle, exactly as the forward found it.
+ * p_i, d_i and lambda are recomputed exactly (FP64 from the float32 inputs)
+ * for the triangle d_tri[i], as the forward computed them for its winner:
+ * the forward's rounded closest point and distance would give the direction
+ * (q - p) / d only to about 1e-7 / d (norm-wise 2.5e-3 on 4M near-surface
+ * points, measured), so they are not inputs.
+ *   d_tri:           device, n int32: the forward's triangle ids
  *   d_grad_dist:     device, n float32
  *   d_grad_points:   device, n x 3 float32 (nullable), overwritten
  *   d_grad_vertices: device, n_vertices x 3 float32 (nullable), accumulated
  *                    with float32 atomics (caller zeroes it) */
-int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n,
-                           const int32_t* d_tri, const float* d_closest, const float* d_dist,
-                           const float* d_grad_dist, float* d_grad_points,
-                           float* d_grad_vertices, void* stream);
+int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n, const int32_t* d_tri,
+                           const float* d_grad_dist, float* d_grad_points, float* d_grad_vertices,
+                           void* stream);
 
 /* p2m_query_backward visiting the points in the caller's order (nullable:
  * input order), e.g. the d_order p2m_sort_points wrote for the forward pass,

@@ -114,14 +114,15 @@ class Mesh:
         c = _lib.p2m_query_config()
         check(lib().p2m_get_query_config(self.handle, ctypes.byref(c)))
         return {"block_size": c.block_size, "reorder": c.reorder, "xcd_groups": c.xcd_groups,
-                "sort_bits": c.sort_bits}
+                "sort_bits": c.sort_bits, "stage": c.stage}
 
-    def set_query_config(self, block_size=None, reorder=None, xcd_groups=None, sort_bits=None):
+    def set_query_config(self, block_size=None, reorder=None, xcd_groups=None, sort_bits=None, stage=None):
         cur = self.query_config()
         c = _lib.p2m_query_config(block_size if block_size is not None else cur["block_size"],
                                   int(reorder) if reorder is not None else cur["reorder"],
                                   xcd_groups if xcd_groups is not None else cur["xcd_groups"],
-                                  sort_bits if sort_bits is not None else cur["sort_bits"])
+                                  sort_bits if sort_bits is not None else cur["sort_bits"],
+                                  int(stage) if stage is not None else cur["stage"])
         check(lib().p2m_set_query_config(self.handle, ctypes.byref(c)))
 
     def host_sites(self):
@@ -329,29 +330,23 @@ def query_touched(mesh, points, stream=None):
     return dist, tri, closest, dict(zip(COUNTER_NAMES, c)), touched
 
 
-def query_backward(mesh, points, tri, grad_dist, grad_points=True, grad_vertices=None, order=None,
-                   closest=None, dist=None, stream=None):
+def query_backward(mesh, points, tri, grad_dist, grad_points=True, grad_vertices=None, order=None, stream=None):
     """Gradients of ``sum(grad_dist * dist)``: ``(dL/dpoints, dL/dV)``.
     ``grad_vertices`` may be a zeroed (nV, 3) tensor to accumulate into.
     ``order``: the visiting order ``sort_points`` gave for the forward pass
     (``p2m_query_backward_ordered``); without it the points are sorted again
-    when dL/dV is wanted.  ``closest`` and ``dist`` (both or neither, not
-    with ``order``): the forward's outputs, from which dL/dq is formed."""
+    when dL/dV is wanted."""
     import torch
     p = _check_points(mesh, points)
     n = p.shape[0]
     g = grad_dist.contiguous().to(torch.float32)
     gq = torch.empty((n, 3), dtype=torch.float32, device=p.device) if grad_points else None
     if order is not None:
-        if closest is not None or dist is not None:
-            raise ValueError("closest/dist are taken by the unordered backward only")
         check(lib().p2m_query_backward_ordered(mesh.handle, _ptr(p), _ptr(order), n, _ptr(tri.contiguous()),
                                                _ptr(g), _ptr(gq), _ptr(grad_vertices), _stream(stream)))
     else:
-        cl = closest.contiguous() if closest is not None else None
-        dd = dist.contiguous() if dist is not None else None
-        check(lib().p2m_query_backward(mesh.handle, _ptr(p), n, _ptr(tri.contiguous()), _ptr(cl), _ptr(dd),
-                                       _ptr(g), _ptr(gq), _ptr(grad_vertices), _stream(stream)))
+        check(lib().p2m_query_backward(mesh.handle, _ptr(p), n, _ptr(tri.contiguous()), _ptr(g), _ptr(gq),
+                                       _ptr(grad_vertices), _stream(stream)))
     return gq, grad_vertices
 
 

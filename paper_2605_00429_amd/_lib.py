@@ -33,7 +33,7 @@ class p2m_mesh_desc(ctypes.Structure):
 class p2m_build_opts(ctypes.Structure):
     _fields_ = [("domain_scale", ctypes.c_float), ("augment", ctypes.c_int32),
                 ("tau_scale", ctypes.c_float), ("dense_min_sites", ctypes.c_int32),
-                ("dense_rel", ctypes.c_float), ("ring_sites", ctypes.c_int32),
+                ("dense_rel", ctypes.c_float), ("ring_sites", ctypes.c_int32), ("ring_layers", ctypes.c_int32),
                 ("aux_list_mode", ctypes.c_int32), ("list_inflation_rel", ctypes.c_float),
                 ("seed_cell_scale", ctypes.c_float), ("seed_max_cells", ctypes.c_int64),
                 ("n_threads", ctypes.c_int32), ("decomposition", ctypes.c_int32),
@@ -64,7 +64,7 @@ class p2m_stats(ctypes.Structure):
 
 class p2m_query_config(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("reorder", ctypes.c_int32), ("xcd_groups", ctypes.c_int32),
-                ("sort_bits", ctypes.c_int32)]
+                ("sort_bits", ctypes.c_int32), ("stage", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p
@@ -81,7 +81,7 @@ SIGNATURES = {
     "p2m_point_set_distance": (_I32, [_VP, _VP, _I64, _VP, _VP]),
     "p2m_mesh_distance": (_I32, [_VP, _VP, _VP, _I64, _VP, _I64, _VP, _VP]),
     "p2m_query_touched": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP]),
-    "p2m_query_backward": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "p2m_query_backward": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP]),
     "p2m_query_backward_ordered": (_I32, [_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP]),
     "p2m_query_fused": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "p2m_get_stats": (_I32, [_VP, ctypes.POINTER(p2m_stats)]),

@@ -66,7 +66,7 @@ struct p2m_handle_ {
     p2m::DevMesh dm{};
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
-    p2m_query_config cfg{256, 1, 1, 0};
+    p2m_query_config cfg{256, 1, 1, 0, 1};
     // the caller's referenced vertices (index order), for mesh distances
     const float* ref_v = nullptr;
     int64_t n_ref = 0;
@@ -125,6 +125,11 @@ struct p2m_handle_ {
         dm.tri_rec = upload<float4>(h.tri_rec.data(), h.tri_rec.size() * 4);
         dm.tri_user = upload<int32_t>(h.tri_user.data(), h.tri_user.size() * 4);
         dm.tri_vid = upload<int4>(h.tri_vid.data(), h.tri_vid.size() * 4);
+        {
+            std::vector<float> v4(4 * (size_t)mesh.n_vertices, 0.f);
+            for (int64_t v = 0; v < mesh.n_vertices; ++v) std::memcpy(&v4[4 * v], mesh.vertices + 3 * v, 12);
+            dm.verts = upload<float4>(v4.data(), v4.size() * 4);
+        }
         std::vector<int32_t> slot(h.n_triangles);
         for (int64_t i = 0; i < h.n_triangles; ++i) slot[h.tri_user[i]] = (int32_t)i;
         dm.tri_slot = upload<int32_t>(slot.data(), slot.size() * 4);
@@ -216,6 +221,7 @@ void p2m_default_opts(p2m_build_opts* o)
     o->dense_min_sites = 256;
     o->dense_rel = 8.0f;
     o->ring_sites = 12;
+    o->ring_layers = 8;
     o->aux_list_mode = 1;
     o->gpu_lists = 1;
     o->decomposition = 0;
@@ -308,6 +314,7 @@ int32_t p2m_set_query_config(p2m_handle h, const p2m_query_config* c)
         return fail(P2M_ERR_INVALID_ARG, "xcd_groups must be in [1, 64]");
     if (c->sort_bits < 0 || c->sort_bits > 8)
         return fail(P2M_ERR_INVALID_ARG, "sort_bits must be in [0, 8]");
+    if (c->stage != 0 && c->stage != 1) return fail(P2M_ERR_INVALID_ARG, "stage must be 0 or 1");
     h->cfg = *c;
     return P2M_OK;
 }
@@ -337,6 +344,7 @@ static int32_t query_common(p2m_handle h, const float* q, int64_t n, float* dist
     a.ctr = ctr;
     if (touch) a.touch = *touch;
     a.xcds = h->cfg.xcd_groups;
+    a.stage = h->cfg.stage;
     std::lock_guard<std::recursive_mutex> lk(h->mu);
     if (h->cfg.reorder) {
         // The search gathers each point through the order: measured faster
@@ -462,6 +470,7 @@ int32_t p2m_query_ordered(p2m_handle h, const float* d_points, const int32_t* d_
     a.tri = d_out_tri;
     a.closest = d_out_closest;
     a.xcds = h->cfg.xcd_groups;
+    a.stage = h->cfg.stage;
     hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, false, false, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return P2M_OK;
@@ -486,6 +495,7 @@ int32_t p2m_query_sorted(p2m_handle h, const float* d_sorted_points, const int32
     a.tri = d_out_tri;
     a.closest = d_out_closest;
     a.xcds = h->cfg.xcd_groups;
+    a.stage = h->cfg.stage;
     hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, false, false, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return P2M_OK;
@@ -567,12 +577,9 @@ int32_t p2m_query_fused(p2m_handle h, const float* d_points, int64_t n, const fl
 }
 
 int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n, const int32_t* d_tri,
-                           const float* d_closest, const float* d_dist, const float* d_grad_dist,
-                           float* d_grad_points, float* d_grad_vertices, void* stream)
+                           const float* d_grad_dist, float* d_grad_points, float* d_grad_vertices, void* stream)
 {
     if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
-    if ((d_closest == nullptr) != (d_dist == nullptr))
-        return fail(P2M_ERR_INVALID_ARG, "pass both the closest points and the distances, or neither");
     if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
     if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
     if (n == 0) return P2M_OK;
@@ -591,8 +598,8 @@ int32_t p2m_query_backward(p2m_handle h, const float* d_points, int64_t n, const
         hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->cfg.sort_bits, ws, &order, st);
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
     }
-    hipError_t e = p2m::launch_backward(h->dm, d_points, n, order, d_tri, d_closest, d_dist, d_grad_dist,
-                                        d_grad_points, d_grad_vertices, h->cfg.block_size, st);
+    hipError_t e = p2m::launch_backward(h->dm, d_points, n, order, d_tri, d_grad_dist, d_grad_points,
+                                        d_grad_vertices, h->cfg.block_size, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return P2M_OK;
 }
@@ -608,8 +615,8 @@ int32_t p2m_query_backward_ordered(p2m_handle h, const float* d_points, const in
     if (!d_points || !d_tri || !d_grad_dist) return fail(P2M_ERR_INVALID_ARG, "null points, triangles or gradient");
     if (n > 0x7fffffffLL) return fail(P2M_ERR_INVALID_ARG, "more than 2^31-1 points per call");
     DeviceGuard dg(h->device);
-    hipError_t e = p2m::launch_backward(h->dm, d_points, n, d_order, d_tri, nullptr, nullptr, d_grad_dist,
-                                        d_grad_points, d_grad_vertices, h->cfg.block_size, (hipStream_t)stream);
+    hipError_t e = p2m::launch_backward(h->dm, d_points, n, d_order, d_tri, d_grad_dist, d_grad_points,
+                                        d_grad_vertices, h->cfg.block_size, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return P2M_OK;
 }

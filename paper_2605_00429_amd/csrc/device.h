@@ -17,6 +17,7 @@ struct DevMesh {
     const float4* tri_rec;   // 3 per slot: (a, |e1|^2), (e1, e1.e2), (e2, |e2|^2)
     const int32_t* tri_user; // slot -> caller triangle id
     const int4* tri_vid;     // caller triangle id -> caller vertex ids
+    const float4* verts;     // caller vertices (x, y, z, 0): the winner's exact FP64 closest point
     const int32_t* tri_slot; // caller triangle id -> slot
     const int32_t* seed;     // seed grid (x fastest)
     const float4* bvh;       // 2 per node
@@ -65,6 +66,7 @@ struct FwdArgs {
     Touch touch;             // counters only: distinct items read (see Touch)
     int32_t xcds;            // blocks are spread over this many XCD groups (see launch_forward)
     int32_t acc_slots;       // fused: LDS hash slots for vertex gradients (set by launch_forward)
+    int32_t stage;           // 1: stage the located sites' list spheres in LDS before the scan
 };
 
 // Arguments of the persistent batched kernel.  Queries of mesh i occupy
@@ -91,13 +93,12 @@ hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int
                         hipStream_t st);
 hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fused, bool counters,
                           hipStream_t st);
-// order (nullable): visit point order[j] at thread j.  closest and dist
-// (nullable, both or neither): the forward's outputs, from which dL/dq is
-// formed; without them, and for the barycentrics dL/dV needs, the closest
-// point is recomputed from the triangle.
+// order (nullable): visit point order[j] at thread j.  The closest point
+// of each point's triangle is recomputed exactly (FP64), as the forward
+// computed it for its winner.
 hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* order,
-                           const int32_t* tri, const float* closest, const float* dist, const float* g,
-                           float* grad_q, float* grad_v, int block, hipStream_t st);
+                           const int32_t* tri, const float* g, float* grad_q, float* grad_v, int block,
+                           hipStream_t st);
 // Radix sort of queries by the Morton code of their cell in a 2^k grid
 // over the seed-grid box (k from n when bits = 0).  ws must hold
 // reorder_workspace_bytes(n) bytes; writes the order to *perm_out.

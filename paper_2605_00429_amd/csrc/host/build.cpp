@@ -200,6 +200,112 @@ void voronoi_cell(int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo,
     w.cell.face_ids(w.faces);
 }
 
+// Eigenvectors of a symmetric 3x3 matrix (xx, xy, xz, yy, yz, zz) by
+// cyclic Jacobi rotations; returns the eigenvalues in w and the vectors as
+// the columns of v.
+void sym3_eigen(const double c[6], double w[3], double v[3][3])
+{
+    double a[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) v[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        const double on = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (off <= 1e-30 * on || off == 0.0) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double th = 0.5 * std::atan2(2.0 * a[p][q], a[q][q] - a[p][p]);
+                const double cs = std::cos(th), sn = std::sin(th);
+                for (int k = 0; k < 3; ++k) {  // columns p, q
+                    const double kp = a[k][p], kq = a[k][q];
+                    a[k][p] = cs * kp - sn * kq;
+                    a[k][q] = sn * kp + cs * kq;
+                }
+                for (int k = 0; k < 3; ++k) {  // rows p, q
+                    const double pk = a[p][k], qk = a[q][k];
+                    a[p][k] = cs * pk - sn * qk;
+                    a[q][k] = sn * pk + cs * qk;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double kp = v[k][p], kq = v[k][q];
+                    v[k][p] = cs * kp - sn * kq;
+                    v[k][q] = sn * kp + cs * kq;
+                }
+            }
+    }
+    for (int i = 0; i < 3; ++i) w[i] = a[i][i];
+}
+
+// A cluster of Voronoi vertices is read as a line (the axis of a cylinder,
+// a cone or a latitude-ring stack, or locally the core circle of a torus)
+// when its covariance has one eigenvalue at least four times the next;
+// then *axis is that eigenvector.
+bool elongated_axis(const double cov[6], d3& axis)
+{
+    double w[3], v[3][3];
+    sym3_eigen(cov, w, v);
+    int i0 = 0;
+    for (int i = 1; i < 3; ++i)
+        if (w[i] > w[i0]) i0 = i;
+    double second = -INFINITY;
+    for (int i = 0; i < 3; ++i)
+        if (i != i0) second = std::max(second, w[i]);
+    if (!(w[i0] > 0.0) || w[i0] < 4.0 * std::max(second, 0.0)) return false;
+    axis = d3{v[0][i0], v[1][i0], v[2][i0]};
+    const double n = norm(axis);
+    if (!(n > 0)) return false;
+    axis = axis * (1.0 / n);
+    return true;
+}
+
+// Auxiliary sites of one dense cluster at pc, whose distance to the mesh is
+// d_wall: layers at radii d_wall / 2, d_wall / 4, ... (at least tau, at
+// most `layers` of them; one layer at d_wall / 2 when that is below tau).
+// A line cluster (axis given) gets rings in the plane through pc normal to
+// the axis, a point cluster spherical shells, each with sites about tau
+// apart (rings at least min_ring sites).  Vertex cells that reached the
+// cluster end at the outermost layer, where each ring site's cell spans a
+// small angle about the cluster, so that no cell near the cluster keeps a
+// corner from which the whole surrounding wall is almost equidistant.
+template <class Emit>
+void ring_layer_sites(d3 pc, const d3* axis, double d_wall, double tau, int layers, int min_ring, Emit emit)
+{
+    double rho = 0.5 * d_wall;
+    if (!(rho > 0)) return;
+    d3 u{1, 0, 0}, v{0, 1, 0};
+    if (axis) {
+        const d3 a = *axis;
+        const d3 e = std::fabs(a.x) < 0.6 ? d3{1, 0, 0} : (std::fabs(a.y) < 0.6 ? d3{0, 1, 0} : d3{0, 0, 1});
+        u = cross(a, e);
+        u = u * (1.0 / norm(u));
+        v = cross(a, u);
+    }
+    for (int k = 0; k < layers; ++k) {
+        if (k > 0 && rho < tau) break;
+        if (axis) {
+            const int m = std::max(min_ring, (int)std::ceil(2.0 * M_PI * rho / tau));
+            const double sep = 0.5 * std::min(tau, 2.0 * M_PI * rho / m);
+            const double off = (k % 2) ? 0.5 : 0.0;
+            for (int j = 0; j < m; ++j) {
+                const double ph = 2.0 * M_PI * (j + off) / m;
+                emit(pc + (u * std::cos(ph) + v * std::sin(ph)) * rho, sep);
+            }
+        } else {
+            const int m = std::max(12, (int)std::ceil(4.0 * M_PI * rho * rho / (tau * tau)));
+            const double sep = 0.5 * std::min(tau, rho * std::sqrt(4.0 * M_PI / m));
+            for (int j = 0; j < m; ++j) {
+                // golden-spiral directions
+                const double z = 1.0 - 2.0 * (j + 0.5) / m;
+                const double r = std::sqrt(std::max(0.0, 1.0 - z * z));
+                const double ph = j * 2.399963229728653 + 0.5 * k;
+                emit(pc + d3{r * std::cos(ph), r * std::sin(ph), z} * rho, sep);
+            }
+        }
+        rho *= 0.5;
+    }
+}
+
 void check_mesh(const p2m_mesh_desc& m)
 {
     if (m.n_vertices < 0 || m.n_triangles < 0) throw Error(P2M_ERR_INVALID_ARG, "negative mesh size");
@@ -221,7 +327,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
 {
     const auto t_start = clk::now();
     check_mesh(mesh);
-    if (!(o.domain_scale >= 1.0f) || !(o.tau_scale > 0) || o.ring_sites < 0 ||
+    if (!(o.domain_scale >= 1.0f) || !(o.tau_scale > 0) || o.ring_sites < 0 || o.ring_layers < 0 ||
         !(o.list_inflation_rel >= 0) || !(o.seed_cell_scale > 0) || o.seed_max_cells < 1 ||
         o.decomposition < 0 || o.decomposition > 1 || o.octree_max_list < 1 || o.octree_max_depth < 0 ||
         o.octree_max_depth > 16)
@@ -343,6 +449,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             int64_t nc = 0;      // Voronoi-vertex occurrences
             d3 s{0, 0, 0};
             double s2 = 0;
+            double m[6] = {0, 0, 0, 0, 0, 0};  // second moments xx, xy, xz, yy, yz, zz
         };
         std::vector<std::unordered_map<uint64_t, Acc>> maps(nth);
         const double tolb = 1e-9 * norm(bhi - blo);
@@ -382,8 +489,15 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
                 Acc& a = maps[tid][kc[i].first];
                 if (i == 0 || kc[i].first != kc[i - 1].first) a.n++;
                 a.nc++;
-                a.s = a.s + kc[i].second;
-                a.s2 += norm2(kc[i].second);
+                const d3 u = kc[i].second;
+                a.s = a.s + u;
+                a.s2 += norm2(u);
+                a.m[0] += u.x * u.x;
+                a.m[1] += u.x * u.y;
+                a.m[2] += u.x * u.z;
+                a.m[3] += u.y * u.y;
+                a.m[4] += u.y * u.z;
+                a.m[5] += u.z * u.z;
             }
         });
         for (int t = 1; t < nth; ++t)
@@ -393,6 +507,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
                 a.nc += kv.second.nc;
                 a.s = a.s + kv.second.s;
                 a.s2 += kv.second.s2;
+                for (int k = 0; k < 6; ++k) a.m[k] += kv.second.m[k];
             }
         t_vor1 = secs_since(t0);
         // Reference density: grid cells that hold mesh vertices (the
@@ -444,10 +559,28 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             ++n_dense;
             const Acc& a = c.second;
             const d3 pc = a.s * (1.0 / a.nc);
-            const double rms = std::sqrt(std::max(0.0, a.s2 / a.nc - norm2(pc)));
-            const double rho = std::min(std::max(3.0 * rms, tau), 3.0 * tau);
             centrals.push_back({pc, 0.5 * tau});
-            for (const d3& d : dirs) rings.push_back({pc + d * rho, 0.5 * rho});
+            if (o.ring_layers <= 0) {
+                // one enclosing sphere of ring_sites sites
+                const double rms = std::sqrt(std::max(0.0, a.s2 / a.nc - norm2(pc)));
+                const double rho = std::min(std::max(3.0 * rms, tau), 3.0 * tau);
+                for (const d3& d : dirs) rings.push_back({pc + d * rho, 0.5 * rho});
+                continue;
+            }
+            // Layered rings (see ring_layer_sites): the cluster's shape from
+            // the covariance of its Voronoi vertices, the free radius from the
+            // distance to the mesh.
+            double cov[6];
+            const double inv_n = 1.0 / (double)a.nc;
+            const double mm[6] = {pc.x * pc.x, pc.x * pc.y, pc.x * pc.z, pc.y * pc.y, pc.y * pc.z, pc.z * pc.z};
+            for (int k = 0; k < 6; ++k) cov[k] = a.m[k] * inv_n - mm[k];
+            d3 axis;
+            const bool line = elongated_axis(cov, axis);
+            int32_t ct;
+            d3 cp;
+            const double d_wall = std::sqrt(bvh.closest(pc, &ct, &cp));
+            ring_layer_sites(pc, line ? &axis : nullptr, d_wall, tau, o.ring_layers, std::max(o.ring_sites, 8),
+                             [&](d3 p, double sep) { rings.push_back({p, sep}); });
         }
         // accept centrals first, then ring sites; the overlap rule drops a
         // candidate within its separation radius of an accepted one

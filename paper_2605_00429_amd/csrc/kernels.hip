@@ -33,13 +33,17 @@ namespace {
 constexpr float kInf = __builtin_huge_valf();
 constexpr int kWalkCap = 4096;
 
-// Closest point of the triangle record (a, e1, e2 with Gram entries) to q,
-// by classifying q against the triangle's vertex, edge and face regions
-// (Ericson, Real-Time Collision Detection, Sec. 5.1.5).  The region tests
-// are evaluated for all regions and resolved with selects, so lanes in
-// different regions do not diverge; reciprocals use the 1-ulp hardware
-// instruction.  Returns the squared distance and the barycentric weights
-// (v, w) of b and c.
+// Squared distance from q to the triangle (a, a + e1, a + e2), float32, as
+// the search uses it to compare triangles: q is classified against the
+// triangle's vertex, edge and face regions (Ericson, Real-Time Collision
+// Detection, Sec. 5.1.5), all regions evaluated and resolved with selects
+// so that lanes in different regions do not diverge; reciprocals use the
+// 1-ulp hardware instruction.  In the face region the distance is the
+// plane distance (n.(q - a))^2 / |n|^2 with n = e1 x e2: on long thin
+// triangles (a fan of 512 slivers around a cap centre) the barycentric
+// products cancel and the residual q - a - v e1 - w e2 keeps an in-plane
+// error of up to 2e-4 of the edge length, where the plane distance stays
+// within a few 1e-6.  Also returns the barycentric weights (v, w) of b and c.
 __device__ __forceinline__ float closest_point(const float3 q, const float3 a, const float3 e1, const float3 e2,
                                                const float g12, float& v, float& w)
 {
@@ -81,7 +85,8 @@ __device__ __forceinline__ float closest_point(const float3 q, const float3 a, c
     if (d1 <= 0.f && d2 <= 0.f) {                 // vertex a
         vv = 0.f; ww = 0.f; face = false;
     }
-    if (face && !(den > 0.f && den < kInf)) {
+    const bool flat = !(den > 0.f && den < kInf);
+    if (face && flat) {
         // zero-area triangle: best of its three edges (rare)
         const float g11 = r0.w, g12 = r1.w, g22 = r2.w;
         const float t0 = g11 > 0.f ? fminf(fmaxf(d1 / g11, 0.f), 1.f) : 0.f;      // a + t e1
@@ -101,10 +106,107 @@ __device__ __forceinline__ float closest_point(const float3 q, const float3 a, c
     }
     v = vv;
     w = ww;
+    if (face && !flat) {
+        // plane distance: n = e1 x e2, h = n . (q - a)
+        const float nx = r1.y * r2.z - r1.z * r2.y;
+        const float ny = r1.z * r2.x - r1.x * r2.z;
+        const float nz = r1.x * r2.y - r1.y * r2.x;
+        const float h = nx * apx + ny * apy + nz * apz;
+        return h * h * __builtin_amdgcn_rcpf(nx * nx + ny * ny + nz * nz);
+    }
     const float rx = apx - vv * r1.x - ww * r2.x;
     const float ry = apy - vv * r1.y - ww * r2.y;
     const float rz = apz - vv * r1.z - ww * r2.z;
     return rx * rx + ry * ry + rz * rz;
+}
+
+// Closest point of the triangle (a, b, c) to q in FP64, for the one
+// triangle a query's search has chosen: the same region classification on
+// the exact float32 inputs promoted to double, so that the reported
+// distance, closest point and gradient direction are those of the chosen
+// triangle to ~1e-15 relative, even for points within 1e-7 of the surface.
+// Returns the squared distance and the barycentric weights (v, w) of b
+// and c.
+__device__ __noinline__ double closest_point64(const double3 q, const double3 a, const double3 b, const double3 c,
+                                               double& v, double& w)
+{
+    const double e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
+    const double e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
+    const double apx = q.x - a.x, apy = q.y - a.y, apz = q.z - a.z;
+    const double g11 = e1x * e1x + e1y * e1y + e1z * e1z;
+    const double g22 = e2x * e2x + e2y * e2y + e2z * e2z;
+    const double g12 = e1x * e2x + e1y * e2y + e1z * e2z;
+    const double d1 = e1x * apx + e1y * apy + e1z * apz;
+    const double d2 = e2x * apx + e2y * apy + e2z * apz;
+    const double d3 = d1 - g11, d4 = d2 - g12, d5 = d1 - g12, d6 = d2 - g22;
+    double vv, ww;
+    if (d1 <= 0.0 && d2 <= 0.0) {                               // vertex a
+        vv = 0.0; ww = 0.0;
+    } else if (d3 >= 0.0 && d4 <= d3) {                         // vertex b
+        vv = 1.0; ww = 0.0;
+    } else {
+        const double vc = d1 * d4 - d3 * d2;
+        const double vb = d5 * d2 - d1 * d6;
+        const double va = d3 * d6 - d5 * d4;
+        if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {             // edge ab
+            vv = d1 / (d1 - d3); ww = 0.0;
+        } else if (d6 >= 0.0 && d5 <= d6) {                    // vertex c
+            vv = 0.0; ww = 1.0;
+        } else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {       // edge ca
+            vv = 0.0; ww = d2 / (d2 - d6);
+        } else if (va <= 0.0 && d4 - d3 >= 0.0 && d5 - d6 >= 0.0) {  // edge bc
+            const double t = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+            vv = 1.0 - t; ww = t;
+        } else {
+            const double den = va + vb + vc;
+            if (den > 0.0 && den < 1e308) {                     // face
+                vv = vb / den; ww = vc / den;
+            } else {
+                // zero-area triangle: best of its three edges
+                const double t0 = g11 > 0.0 ? fmin(fmax(d1 / g11, 0.0), 1.0) : 0.0;
+                const double t1 = g22 > 0.0 ? fmin(fmax(d2 / g22, 0.0), 1.0) : 0.0;
+                const double g33 = g11 - 2.0 * g12 + g22;
+                const double t2 = g33 > 0.0 ? fmin(fmax((d2 - d1 - g12 + g11) / g33, 0.0), 1.0) : 0.0;
+                auto dist2 = [&](double a1, double a2) {
+                    const double rx = apx - a1 * e1x - a2 * e2x;
+                    const double ry = apy - a1 * e1y - a2 * e2y;
+                    const double rz = apz - a1 * e1z - a2 * e2z;
+                    return rx * rx + ry * ry + rz * rz;
+                };
+                const double s0 = dist2(t0, 0.0), s1 = dist2(0.0, t1), s2 = dist2(1.0 - t2, t2);
+                if (s0 <= s1 && s0 <= s2) { vv = t0; ww = 0.0; }
+                else if (s1 <= s2) { vv = 0.0; ww = t1; }
+                else { vv = 1.0 - t2; ww = t2; }
+            }
+        }
+    }
+    v = vv;
+    w = ww;
+    const double rx = apx - vv * e1x - ww * e2x;
+    const double ry = apy - vv * e1y - ww * e2y;
+    const double rz = apz - vv * e1z - ww * e2z;
+    return rx * rx + ry * ry + rz * rz;
+}
+
+// The chosen triangle's exact closest point: its caller vertices from the
+// vertex array (float32 inputs, exact in double), closest_point64, and the
+// point p = a + v (b - a) + w (c - a), all in FP64.
+struct Final {
+    double d2, v, w;
+    double3 p;
+};
+
+__device__ __forceinline__ Final finalize(const DevMesh& m, const float3 q, const int user)
+{
+    const int4 vid = m.tri_vid[user];
+    const float4 fa = m.verts[vid.x], fb = m.verts[vid.y], fc = m.verts[vid.z];
+    const double3 a = make_double3(fa.x, fa.y, fa.z), b = make_double3(fb.x, fb.y, fb.z),
+                  c = make_double3(fc.x, fc.y, fc.z);
+    Final f;
+    f.d2 = closest_point64(make_double3(q.x, q.y, q.z), a, b, c, f.v, f.w);
+    f.p = make_double3(a.x + f.v * (b.x - a.x) + f.w * (c.x - a.x), a.y + f.v * (b.y - a.y) + f.w * (c.y - a.y),
+                       a.z + f.v * (b.z - a.z) + f.w * (c.z - a.z));
+    return f;
 }
 
 // The same test on a triangle record (|e1|^2, |e2|^2 in the record are not
@@ -257,7 +359,8 @@ constexpr int kChunk = 4;
 // entry (else -1).
 template <bool kCtr>
 __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, const float4 sp, const int4 rg,
-                                            const int budget, int* resume, QueryCounts& n, const Touch& tch)
+                                            const int budget, int* resume, QueryCounts& n, const Touch& tch,
+                                            const float4* st = nullptr, const int st_off = 0, const int st_cnt = 0)
 {
     const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
     // |q - s| rounded up so that the early-exit bound stays conservative
@@ -274,12 +377,18 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
         }
         // the spheres (c, r) of kChunk entries, from the dense sphere array;
         // an entry's record (a, e1, e2) is read for an exact test only
+        // (the first st_cnt of them staged in LDS at st + st_off)
         float4 c[kChunk];
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             const int idx = min(e + k, rg.w - 1);
-            c[k] = m.list_sph[idx];
-            if (kCtr && tch.sph) tch.sph[idx] = 1;
+            const int sk = idx - rg.z;
+            if (sk < st_cnt) {
+                c[k] = st[st_off + sk];
+            } else {
+                c[k] = m.list_sph[idx];
+                if (kCtr && tch.sph) tch.sph[idx] = 1;
+            }
         }
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
@@ -634,49 +743,34 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
             grad_q[3 * i + 2] = 0.f;
         }
     } else if (valid) {
-        // the winner's vertex a, edges e1, e2 and caller id: from its list
-        // entry (just scanned, so cache-resident), or from the triangle records
-        float4 r0, r1, r2;
-        int user;
-        if (b.idx >= 0) {
-            const float4* L = m.list_rec + 3 * (int64_t)b.idx;
-            r0 = L[0];
-            r1 = L[1];
-            r2 = L[2];
-            user = __float_as_int(r2.w);
-        } else {
-            const int slot = -b.idx - 2;
-            const float4* r = m.tri_rec + 3 * (int64_t)slot;
-            r0 = r[0];
-            r1 = r[1];
-            r2 = r[2];
-            user = m.tri_user[slot];
-        }
-        const float d = sqrtf(b.d2);
-        dist[i] = d;
+        // the winner's caller id (from its list entry, just scanned, or the
+        // fallback's slot), then its exact closest point in FP64
+        const int user = b.idx >= 0 ? __float_as_int(m.list_rec[3 * (int64_t)b.idx + 2].w) : m.tri_user[-b.idx - 2];
+        const Final f = finalize(m, q, user);
+        const double d = sqrt(f.d2);
+        dist[i] = (float)d;
         if (tri) tri[i] = user;
         if (closest) {
-            closest[3 * i] = r0.x + b.v * r1.x + b.w * r2.x;
-            closest[3 * i + 1] = r0.y + b.v * r1.y + b.w * r2.y;
-            closest[3 * i + 2] = r0.z + b.v * r1.z + b.w * r2.z;
+            closest[3 * i] = (float)f.p.x;
+            closest[3 * i + 1] = (float)f.p.y;
+            closest[3 * i + 2] = (float)f.p.z;
         }
         if (kFused) {
             const float g = gdist[i];
             float nx = 0.f, ny = 0.f, nz = 0.f;
-            if (d > 0.f) {
-                // (q - p) / d from the same residual the distance came from
-                const float inv = 1.f / d;
-                nx = (q.x - r0.x - b.v * r1.x - b.w * r2.x) * inv;
-                ny = (q.y - r0.y - b.v * r1.y - b.w * r2.y) * inv;
-                nz = (q.z - r0.z - b.v * r1.z - b.w * r2.z) * inv;
+            if (d > 0.0) {
+                const double inv = 1.0 / d;
+                nx = (float)((q.x - f.p.x) * inv);
+                ny = (float)((q.y - f.p.y) * inv);
+                nz = (float)((q.z - f.p.z) * inv);
             }
             if (grad_q) {
                 grad_q[3 * i] = g * nx;
                 grad_q[3 * i + 1] = g * ny;
                 grad_q[3 * i + 2] = g * nz;
             }
-            if (d > 0.f && g != 0.f) {
-                const float lam[3] = {1.f - b.v - b.w, b.v, b.w};
+            if (d > 0.0 && g != 0.f) {
+                const float lam[3] = {(float)(1.0 - f.v - f.w), (float)f.v, (float)f.w};
                 gtri = user;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
@@ -833,6 +927,86 @@ __device__ __forceinline__ int64_t xcd_block(const int xcds, const int64_t per)
     return (b % xcds) * per + b / xcds;
 }
 
+// LDS staging of the list spheres a wavefront is about to scan (the
+// "List Search" of Sec. 3.4 reading its candidates from LDS).  After the
+// regroup, lanes holding one site are neighbours; each distinct site of the
+// wavefront gets the first entries of its list copied into the wavefront's
+// kStageEntries-entry area, whole 16-byte spheres, 64 consecutive entries
+// per load instruction, so that one coalesced load serves what 64 per-lane
+// gathers of the scan would have read.  Sites are taken in the order of
+// their first lane until the area (cap entries) is full; a lane's st_off
+// / st_cnt give where its list's first st_cnt entries are (st_cnt = 0: none
+// staged).  Every lane of the wavefront must call it.
+constexpr int kStageEntries = 256;  // largest area per wavefront
+constexpr int kStageUnroll = 4;
+
+template <bool kCtr>
+__device__ __forceinline__ void stage_spheres(const DevMesh& m, float4* st, const int cap, const int s,
+                                              const int4 rg, int& st_off, int& st_cnt, const Touch& tch)
+{
+    const int lane = threadIdx.x & 63;
+    st_off = 0;
+    st_cnt = 0;
+    // the distinct sites: lane g keeps group g's first entry, offset, count
+    int g_first = 0, g_off = 0, g_cnt = 0;
+    int ng = 0, total = 0;
+    for (uint64_t todo = __ballot(s >= 0); todo;) {
+        const int lead = __builtin_ctzll(todo);
+        const int ls = __builtin_amdgcn_readlane(s, lead);
+        const bool mine = s == ls;
+        todo &= ~__ballot(mine);
+        const int lb = __builtin_amdgcn_readlane(rg.z, lead);
+        const int cnt = min(__builtin_amdgcn_readlane(rg.w, lead) - lb, cap - total);
+        if (mine) {
+            st_off = total;
+            st_cnt = cnt;
+        }
+        if (lane == ng) {
+            g_first = lb;
+            g_off = total;
+            g_cnt = cnt;
+        }
+        ++ng;
+        total += cnt;
+    }
+    // flat staged entry f = j + 64 u + lane comes from the group holding it
+    for (int j = 0; j < total; j += 64 * kStageUnroll) {
+        float4 v[kStageUnroll];
+        int f[kStageUnroll];
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u) {
+            f[u] = j + 64 * u + lane;
+            int src = -1;
+            for (int g = 0; g < ng; ++g) {
+                const int go = __builtin_amdgcn_readlane(g_off, g);
+                const int gc = __builtin_amdgcn_readlane(g_cnt, g);
+                if (f[u] >= go && f[u] < go + gc) src = __builtin_amdgcn_readlane(g_first, g) + (f[u] - go);
+            }
+            v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (src >= 0) {
+                v[u] = m.list_sph[src];
+                if (kCtr && tch.sph) tch.sph[src] = 1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageUnroll; ++u)
+            if (f[u] < total) st[f[u]] = v[u];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS of the search kernel before the vertex-gradient table, in ints: the
+// regroup's area, which the staging area (stage entries per wavefront)
+// then reuses.
+__host__ __device__ inline int search_lds_ints(int block, int stage)
+{
+    const int rg = regroup_lds_ints(block);
+    const int sg = (block / 64) * stage * 4;
+    return rg > sg ? rg : sg;
+}
+
 template <bool kFused, bool kCtr>
 __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArgs a)
 {
@@ -844,10 +1018,10 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
     // regroup_by_site), then the list scans.  LDS: the regroup's area, then
     // (fused with dL/dV) the table of vertex gradients, flushed once the
     // workgroup is done.
-    extern __shared__ int smem[];
+    extern __shared__ __align__(16) int smem[];
     const int nw = (int)(blockDim.x >> 6);
     int* rg_smem = smem;
-    int* acc_smem = smem + regroup_lds_ints((int)blockDim.x);
+    int* acc_smem = smem + search_lds_ints((int)blockDim.x, a.stage);
     const bool gv = kFused && a.grad_v;
     const LdsAcc acc{gv ? a.grad_v : nullptr, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
     for (int k = threadIdx.x; k < nw * 256; k += blockDim.x) rg_smem[k] = 0;
@@ -887,10 +1061,18 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
     }
     const bool valid2 = i2 >= 0;
     const bool finite2 = valid2 && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
+    // the located sites' spheres staged in LDS (the area reuses the
+    // regroup's, once every wavefront has read its slot back)
+    int st_off = 0, st_cnt = 0;
+    float4* st = (float4*)smem + (threadIdx.x >> 6) * a.stage;
+    if (a.stage > 0) {
+        __syncthreads();
+        stage_spheres<kCtr>(m, st, a.stage, s, rg, st_off, st_cnt, a.touch);
+    }
     QueryCounts n;
     Best b{kInf, -1, 0.f, 0.f};
     int resume = -1;
-    if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n, a.touch);
+    if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n, a.touch, st, st_off, st_cnt);
     finish_query<kFused, kCtr>(m, valid2, q, finite2, s, b, resume, valid2 ? i2 : 0, a.dist, a.tri, a.closest,
                                a.grad_dist, a.grad_q, acc, a.ctr, n, a.touch);
     if (gv) {
@@ -967,9 +1149,7 @@ __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__
 
 __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float* __restrict__ qp, int64_t n,
                                                    const int32_t* __restrict__ order,
-                                                   const int32_t* __restrict__ tri,
-                                                   const float* __restrict__ closest,
-                                                   const float* __restrict__ dist, const float* __restrict__ gd,
+                                                   const int32_t* __restrict__ tri, const float* __restrict__ gd,
                                                    float* __restrict__ grad_q, float* __restrict__ grad_v,
                                                    int acc_slots, int tiles)
 {
@@ -994,32 +1174,26 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
         if (j < n) {
             const int64_t i = order ? (int64_t)order[j] : j;
             const int tt = tri[i];
-            float nx = 0.f, ny = 0.f, nz = 0.f, g = 0.f, v = 0.f, w = 0.f, d = 0.f;
+            float nx = 0.f, ny = 0.f, nz = 0.f, g = 0.f, d = 0.f;
+            double v = 0.0, w = 0.0;
             if (tt >= 0 && tt < m.n_tris) {
                 const float3 q = make_float3(qp[3 * i], qp[3 * i + 1], qp[3 * i + 2]);
                 g = gd[i];
-                if (closest) {
-                    // (q - p) / d from the forward's outputs; the triangle is
-                    // read only for the barycentrics dL/dV needs
-                    d = dist[i];
-                    if (d > 0.f) {
-                        const float inv = 1.f / d;
-                        nx = (q.x - closest[3 * i]) * inv;
-                        ny = (q.y - closest[3 * i + 1]) * inv;
-                        nz = (q.z - closest[3 * i + 2]) * inv;
-                    }
-                    if (grad_v) (void)closest_point_rec(q, m.tri_rec + 3 * (int64_t)m.tri_slot[tt], v, w);
+                // the triangle's exact closest point, as the forward
+                // computed it for its winner
+                const Final f = finalize(m, q, tt);
+                const double dd = sqrt(f.d2);
+                d = (float)dd;
+                if (dd > 0.0) {
+                    const double inv = 1.0 / dd;
+                    nx = (float)((q.x - f.p.x) * inv);
+                    ny = (float)((q.y - f.p.y) * inv);
+                    nz = (float)((q.z - f.p.z) * inv);
                 } else {
-                    const float4* r = m.tri_rec + 3 * (int64_t)m.tri_slot[tt];
-                    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-                    d = sqrtf(closest_point_rec(q, r, v, w));
-                    if (d > 0.f) {
-                        const float inv = 1.f / d;
-                        nx = (q.x - r0.x - v * r1.x - w * r2.x) * inv;
-                        ny = (q.y - r0.y - v * r1.y - w * r2.y) * inv;
-                        nz = (q.z - r0.z - v * r1.z - w * r2.z) * inv;
-                    }
+                    d = 0.f;
                 }
+                v = f.v;
+                w = f.w;
             }
             if (grad_q) {
                 grad_q[3 * i] = g * nx;
@@ -1027,7 +1201,7 @@ __global__ void __launch_bounds__(1024) bwd_kernel(const DevMesh m, const float*
                 grad_q[3 * i + 2] = g * nz;
             }
             if (d > 0.f && g != 0.f) {
-                const float lam[3] = {1.f - v - w, v, w};
+                const float lam[3] = {(float)(1.0 - v - w), (float)v, (float)w};
                 gtri = tt;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
@@ -1354,7 +1528,9 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
     const unsigned g = (unsigned)(((nb + x - 1) / x) * x);
     FwdArgs args = a;
     args.xcds = x;
-    const size_t rg_bytes = 4 * (size_t)regroup_lds_ints(block);
+    // staging area: up to kStageEntries spheres per wavefront, within 48 KB
+    if (args.stage > 0) args.stage = std::min(kStageEntries, 49152 / (16 * (block / 64)));
+    const size_t rg_bytes = 4 * (size_t)search_lds_ints(block, args.stage);
     if (fused) {
         // the table within 64 KB of LDS together with the regroup's area
         int slots = acc_slots_for(block);
@@ -1371,10 +1547,9 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
 }
 
 hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* order,
-                           const int32_t* tri, const float* closest, const float* dist, const float* g,
-                           float* grad_q, float* grad_v, int block, hipStream_t st)
+                           const int32_t* tri, const float* g, float* grad_q, float* grad_v, int block,
+                           hipStream_t st)
 {
-    if ((closest == nullptr) != (dist == nullptr)) return hipErrorInvalidValue;
     if (n <= 0) return hipSuccess;
     const int slots = acc_slots_capped(kBwdSlotsPerThread * block);
     const size_t lds = grad_v ? acc_lds_bytes(slots) + 16 : 0;
@@ -1393,8 +1568,7 @@ hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const in
         }
     }
     const int64_t grid = (n_tiles + tiles - 1) / tiles;
-    bwd_kernel<<<(unsigned)grid, block, lds, st>>>(m, q, n, order, tri, closest, dist, g, grad_q, grad_v, slots,
-                                                   (int)tiles);
+    bwd_kernel<<<(unsigned)grid, block, lds, st>>>(m, q, n, order, tri, g, grad_q, grad_v, slots, (int)tiles);
     return hipGetLastError();
 }
 

@@ -48,11 +48,12 @@ def test_c0_launch_configs_bitwise(dev, c0):
     for bs in (64, 512, 1024):
         for reorder in (0, 1):
             for xcd in (1, 3, 8):
-                m.set_query_config(block_size=bs, reorder=reorder, xcd_groups=xcd)
-                out = run(dev, m, c["Q"])
-                for a, b in zip(ref, out):
-                    assert np.array_equal(a, b, equal_nan=True), (bs, reorder, xcd)
-    m.set_query_config(block_size=256, reorder=1, xcd_groups=8)
+                for stage in (0, 1):
+                    m.set_query_config(block_size=bs, reorder=reorder, xcd_groups=xcd, stage=stage)
+                    out = run(dev, m, c["Q"])
+                    for a, b in zip(ref, out):
+                        assert np.array_equal(a, b, equal_nan=True), (bs, reorder, xcd, stage)
+    m.set_query_config(block_size=256, reorder=1, xcd_groups=1, stage=1)
 
 
 @pytest.mark.parametrize("n", [1, 4095, 4097, 300_001])
@@ -188,6 +189,26 @@ def test_c2_full_size(dev, c2):
     print("C2 full max|dd|/D, p99.9:", check_full_size(dev, c, m))
 
 
+def test_c2_staging_is_exact(dev, c2):
+    """Staging the list spheres in LDS changes where the scan reads them,
+    not what it computes: 2M points of C2 give bit-identical outputs with
+    and without it, plain and fused, at 256 and 1,024 threads per block."""
+    c, m = c2
+    q = torch.from_numpy(c["Q"][::5].copy()).cuda()
+    g = torch.from_numpy(np.random.default_rng(81).normal(size=len(q)).astype(np.float32)).cuda()
+    outs = {}
+    for bs in (256, 1024):
+        for stage in (0, 1):
+            m.set_query_config(block_size=bs, stage=stage)
+            outs[(bs, stage)] = dev.query(m, q) + dev.query_fused(m, q, g)
+    m.set_query_config(block_size=256, stage=1)
+    torch.cuda.synchronize()
+    ref = outs[(256, 1)]
+    for key, o in outs.items():
+        for a, b in zip(ref, o):
+            assert torch.equal(a, b), key
+
+
 def test_c2_no_walk_reaches_the_step_cap(dev, c2):
     """The instrumented forward on 1M points of C2: no walk stops at the step
     cap, nothing falls back, and the outputs equal the plain forward's."""
@@ -292,9 +313,7 @@ def test_rejects_bad_counts_before_any_launch(dev):
         assert lib.p2m_query(m.handle, p, n, p, None, None, None) == _lib.P2M_ERR_INVALID_ARG
         assert lib.p2m_point_set_distance(m.handle, p, n, p, None) == _lib.P2M_ERR_INVALID_ARG
         assert lib.p2m_sort_points(m.handle, p, n, p, None, None) == _lib.P2M_ERR_INVALID_ARG
-        assert lib.p2m_query_backward(m.handle, p, n, p, None, None, p, None, None, None) == _lib.P2M_ERR_INVALID_ARG
+        assert lib.p2m_query_backward(m.handle, p, n, p, p, None, None, None) == _lib.P2M_ERR_INVALID_ARG
         assert lib.p2m_mesh_distance(m.handle, m.handle, p, n, None, 0, p, None) == _lib.P2M_ERR_INVALID_ARG
     assert lib.p2m_query(m.handle, p, 5, None, None, None, None) == _lib.P2M_ERR_INVALID_ARG   # null distance
-    # closest points without distances (or the reverse) for the backward
-    assert lib.p2m_query_backward(m.handle, p, 5, p, p, None, p, p, None, None) == _lib.P2M_ERR_INVALID_ARG
     assert lib.p2m_mesh_distance(m.handle, m.handle, None, 5, None, 0, p, None) == _lib.P2M_ERR_INVALID_ARG

@@ -143,33 +143,6 @@ def test_c3_full_size_invariants_and_fused(dev, c3):
     assert np.linalg.norm(s) <= 1e-4 * np.abs(gqn).sum()
 
 
-def test_backward_from_forward_outputs(dev, c3):
-    """p2m_query_backward given the forward's closest points and distances
-    forms dL/dq from them (and reads the triangle only for dL/dV): the
-    result agrees with the recomputing backward to float32 rounding, and
-    dL/dV is the same up to the order of float32 additions."""
-    c, m = c3
-    q = torch.from_numpy(c["Q"][:1_000_000]).cuda()
-    g = torch.from_numpy(c["G"][:1_000_000]).cuda()
-    d, t, cl = dev.query(m, q)
-    gv0 = torch.zeros((len(m.V), 3), device="cuda")
-    gq0, gv0 = dev.query_backward(m, q, t, g, grad_vertices=gv0)
-    gv1 = torch.zeros_like(gv0)
-    gq1, gv1 = dev.query_backward(m, q, t, g, grad_vertices=gv1, closest=cl, dist=d)
-    gq2, _ = dev.query_backward(m, q, t, g, closest=cl, dist=d)
-    torch.cuda.synchronize()
-    assert torch.equal(gq1, gq2)
-    a, b = to_np(gq1).astype(np.float64), to_np(gq0).astype(np.float64)
-    # q - p formed from the rounded closest point instead of the residual:
-    # a few float32 roundings of the coordinates (~3e-7 here), relative to d
-    dd, gg = to_np(d), np.abs(to_np(g))
-    far = dd >= 1e-2
-    assert far.sum() > 100_000
-    assert np.all(np.linalg.norm(a - b, axis=1)[far] <= 1e-4 * gg[far] + 1e-12)
-    assert rel_err(a, b) <= 1e-4
-    assert rel_err(to_np(gv1), to_np(gv0)) <= 1e-5
-
-
 def region_key(V, F, Q, tri):
     """Triangle and closest-point region (which barycentrics vanish)."""
     _, _, lam = oracle.distance_to_triangles(V, F, Q, tri)
