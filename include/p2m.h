@@ -150,6 +150,21 @@ int32_t p2m_destroy(p2m_handle h);
 int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
                   int32_t* d_out_tri, float* d_out_closest, void* stream);
 
+/* p2m_query for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same results as p2m_query, with the query sort's workspace taken from
+ * a 32 MiB device array of the library (one per GPU, held until the process
+ * ends) instead of the stream's scratch.  It calls no hipMalloc, hipFree or
+ * allocating library routine.  Point counts whose sort workspace exceeds
+ * the array (about 2,000,000 points at the default settings; roughly 16.25
+ * bytes per point) are refused with P2M_ERR_INVALID_ARG before any launch.
+ * The array needs no clearing between calls (every byte a call reads it
+ * first writes).  All calls on one GPU share it: calls that overlap on one
+ * GPU (on different streams, or from different host threads) race and must
+ * not be issued. */
+int32_t p2m_query_noalloc(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,
+                          int32_t* d_out_tri, float* d_out_closest, void* stream);
+
 /* Distance from a point set to the mesh, reduced on the device: the
  * building block of mesh-to-mesh distance (named as an application in
  * Sec. 5).  With the points sampled on (or the vertices of) a second surface

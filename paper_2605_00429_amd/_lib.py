@@ -78,6 +78,7 @@ SIGNATURES = {
                          ctypes.POINTER(_VP)]),
     "p2m_destroy": (_I32, [_VP]),
     "p2m_query": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP]),
+    "p2m_query_noalloc": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP]),
     "p2m_point_set_distance": (_I32, [_VP, _VP, _I64, _VP, _VP]),
     "p2m_mesh_distance": (_I32, [_VP, _VP, _VP, _I64, _VP, _I64, _VP, _VP]),
     "p2m_query_touched": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP]),

@@ -367,6 +367,73 @@ int32_t p2m_query(p2m_handle h, const float* d_points, int64_t n, float* d_out_d
                         nullptr, false, stream);
 }
 
+// ------------------------------------------------------- no-allocation query
+// Scratch of p2m_query_noalloc: the query sort's workspace, in a device
+// array of the library rather than in memory allocated per call.  Each GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never uses the array's name as an address: its device address is looked
+// up once per device (hipGetSymbolAddress, with that device current) and
+// kept in g_scratch_ptr.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device ordinal; null until looked up
+
+// The scratch array's address on `dev`, which must be the current device.
+int32_t scratch_address(int dev, void** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(P2M_ERR_HIP, "hipGetSymbolAddress(scratch) returned no address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return P2M_OK;
+}
+}  // namespace
+
+int32_t p2m_query_noalloc(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist, int32_t* d_out_tri,
+                          float* d_out_closest, void* stream)
+{
+    if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
+    if (n < 0) return fail(P2M_ERR_INVALID_ARG, "negative point count");
+    if (h->device < 0) return fail(P2M_ERR_NO_DEVICE, "handle was built host-only");
+    if (n == 0) return P2M_OK;
+    if (!d_points || !d_out_dist) return fail(P2M_ERR_INVALID_ARG, "null points or distance output");
+    const size_t need = h->cfg.reorder ? p2m::reorder_workspace_bytes(n, h->cfg.sort_bits) : 0;
+    if (n > 0x7fffffffLL || need > kNoAllocScratchBytes)
+        return fail(P2M_ERR_INVALID_ARG, "p2m_query_noalloc: " + std::to_string(n) + " points need " +
+                                             std::to_string(need) + " bytes of sort workspace; its scratch holds " +
+                                             std::to_string(kNoAllocScratchBytes) + " (use p2m_query)");
+    DeviceGuard dg(h->device);
+    if (!dg.ok) return fail(P2M_ERR_HIP, "cannot select the handle's HIP device");
+    hipStream_t st = (hipStream_t)stream;
+    p2m::FwdArgs a{};
+    a.q = d_points;
+    a.n = n;
+    a.dist = d_out_dist;
+    a.tri = d_out_tri;
+    a.closest = d_out_closest;
+    a.xcds = h->cfg.xcd_groups;
+    a.stage = h->cfg.stage;
+    if (h->cfg.reorder) {
+        void* ws = nullptr;
+        const int32_t rc = scratch_address(h->device, &ws);
+        if (rc != P2M_OK) return rc;
+        const hipError_t e = p2m::launch_reorder(h->dm, d_points, n, h->cfg.sort_bits, ws, &a.perm, st);
+        if (e != hipSuccess) return hip_fail(e, "reorder launch");
+    }
+    const hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, false, false, st);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return P2M_OK;
+}
+
 int32_t p2m_point_set_distance(p2m_handle h, const float* d_points, int64_t n, double* d_out, void* stream)
 {
     if (!h) return fail(P2M_ERR_INVALID_ARG, "null handle");
