@@ -118,10 +118,10 @@ typedef struct {
                            1 (default, measured faster on MI355X) = plain block order */
     int32_t sort_bits;  /* sort grid of 2^sort_bits cells per axis (1..8); 0 = automatic,
                            the finest grid with at most two cells per point */
-    int32_t stage;      /* 1 (default): each wavefront copies the bounding spheres of its
-                           located sites' lists into LDS with coalesced loads before the list
-                           scan (up to 256 per wavefront); 0: the scan gathers them from
-                           device memory.  Results are identical. */
+    int32_t stage;      /* 1: each wavefront copies the bounding spheres of its located sites'
+                           lists into LDS with coalesced loads before the list scan (up to 256
+                           per wavefront); 0 (default, measured faster on MI355X): the scan
+                           gathers them from device memory.  Results are identical. */
 } p2m_query_config;
 
 void p2m_default_opts(p2m_build_opts* opts);

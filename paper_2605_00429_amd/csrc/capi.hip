@@ -66,7 +66,7 @@ struct p2m_handle_ {
     p2m::DevMesh dm{};
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
-    p2m_query_config cfg{256, 1, 1, 0, 1};
+    p2m_query_config cfg{256, 1, 1, 0, 0};
     // the caller's referenced vertices (index order), for mesh distances
     const float* ref_v = nullptr;
     int64_t n_ref = 0;

@@ -30,6 +30,26 @@ struct DevMesh {
     int32_t n_sites, n_tris, n_vertices;
 };
 
+// A load from device memory issued as a global-memory access.  Left to
+// itself the compiler issued the search kernel's loads as flat (generic)
+// ones, which take 64-bit address arithmetic per lane and also wait on the
+// LDS counter.  T is a 4-, 8- or 16-byte type (int, float, int2, float4,
+// int4).
+template <class T>
+__device__ __forceinline__ T gload(const T* p)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "gload: 4, 8 or 16 bytes");
+    if constexpr (sizeof(T) == 16) {
+        typedef int v4 __attribute__((ext_vector_type(4)));
+        return __builtin_bit_cast(T, *(const __attribute__((address_space(1))) v4*)p);
+    } else if constexpr (sizeof(T) == 8) {
+        typedef int v2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(T, *(const __attribute__((address_space(1))) v2*)p);
+    } else {
+        return __builtin_bit_cast(T, *(const __attribute__((address_space(1))) int*)p);
+    }
+}
+
 // Counter slots of the instrumented forward.
 // CTR_WALK_CAP counts walks stopped at the step cap (answered by the exact
 // BVH fallback, so also counted in CTR_FALLBACK).

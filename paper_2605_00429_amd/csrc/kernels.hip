@@ -127,7 +127,7 @@ __device__ __forceinline__ float closest_point(const float3 q, const float3 a, c
 // triangle to ~1e-15 relative, even for points within 1e-7 of the surface.
 // Returns the squared distance and the barycentric weights (v, w) of b
 // and c.
-__device__ __noinline__ double closest_point64(const double3 q, const double3 a, const double3 b, const double3 c,
+__device__ __forceinline__ double closest_point64(const double3 q, const double3 a, const double3 b, const double3 c,
                                                double& v, double& w)
 {
     const double e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
@@ -198,8 +198,8 @@ struct Final {
 
 __device__ __forceinline__ Final finalize(const DevMesh& m, const float3 q, const int user)
 {
-    const int4 vid = m.tri_vid[user];
-    const float4 fa = m.verts[vid.x], fb = m.verts[vid.y], fc = m.verts[vid.z];
+    const int4 vid = gload(m.tri_vid + user);
+    const float4 fa = gload(m.verts + vid.x), fb = gload(m.verts + vid.y), fc = gload(m.verts + vid.z);
     const double3 a = make_double3(fa.x, fa.y, fa.z), b = make_double3(fb.x, fb.y, fb.z),
                   c = make_double3(fc.x, fc.y, fc.z);
     Final f;
@@ -213,7 +213,7 @@ __device__ __forceinline__ Final finalize(const DevMesh& m, const float3 q, cons
 // used: both paths recompute them identically, so results match bitwise).
 __device__ __forceinline__ float closest_point_rec(const float3 q, const float4* r, float& v, float& w)
 {
-    const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+    const float4 r0 = gload(r), r1 = gload(r + 1), r2 = gload(r + 2);
     return closest_point(q, make_float3(r0.x, r0.y, r0.z), make_float3(r1.x, r1.y, r1.z),
                          make_float3(r2.x, r2.y, r2.z), r1.w, v, w);
 }
@@ -237,14 +237,15 @@ __device__ __forceinline__ bool in_domain(const DevMesh& m, const float3 q)
 
 // FP64 value of the bisector predicate (q - s).(t - s) - |t - s|^2 / 2 for
 // every neighbour t of s; the best positive one, or -1.
-__device__ __noinline__ int best_neighbour_f64(const DevMesh& m, const float3 q, const float4 sp, const int4 rg)
+__device__ __noinline__ int best_neighbour_f64(const float4* __restrict__ adj, const float3 q, const float4 sp,
+                                               const int4 rg)
 {
     const double sx = sp.x, sy = sp.y, sz = sp.z;
     const double wx = (double)q.x - sx, wy = (double)q.y - sy, wz = (double)q.z - sz;
     double best = 0.0;
     int nxt = -1;
     for (int k = rg.x; k < rg.y; ++k) {
-        const float4 a = m.adj[k];
+        const float4 a = gload(adj + k);
         const double dx = (double)a.x - sx, dy = (double)a.y - sy, dz = (double)a.z - sz;
         const double val = wx * dx + wy * dy + wz * dz - 0.5 * (dx * dx + dy * dy + dz * dz);
         if (val > best) {
@@ -270,11 +271,11 @@ __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned
                                       const Touch& tch, float4& sp_out, int4& rg_out)
 {
     const int cell = seed_cell(m, q);
-    int s = m.seed[cell];
+    int s = gload(m.seed + cell);
     if (kCtr && tch.seed) tch.seed[cell] = 1;
     for (int it = 0; it < kWalkCap; ++it) {
-        const float4 sp = m.site_rec[2 * s];
-        const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        const float4 sp = gload(m.site_rec + 2 * s);
+        const int4 rg = __builtin_bit_cast(int4, gload(m.site_rec + 2 * s + 1));
         if (kCtr && tch.site) tch.site[s] = 1;
         sp_out = sp;
         rg_out = rg;
@@ -286,7 +287,7 @@ __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned
         for (int k0 = rg.x; k0 < rg.y; k0 += 4) {
             float4 a[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a[k] = m.adj[min(k0 + k, rg.y - 1)];
+            for (int k = 0; k < 4; ++k) a[k] = gload(m.adj + (min(k0 + k, rg.y - 1)));
             if (kCtr && tch.adj)
                 for (int k = 0; k < 4; ++k) tch.adj[min(k0 + k, rg.y - 1)] = 1;
 #pragma unroll
@@ -308,7 +309,7 @@ __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned
             steps += 1;
             adj_read += (unsigned long long)(rg.y - rg.x);
         }
-        if (nxt < 0 && unsure) nxt = best_neighbour_f64(m, q, sp, rg);
+        if (nxt < 0 && unsure) nxt = best_neighbour_f64(m.adj, q, sp, rg);
         if (nxt < 0) return s;
         s = nxt;
     }
@@ -323,14 +324,14 @@ __device__ __forceinline__ int locate(const DevMesh& m, const float3 q, unsigned
 __device__ __forceinline__ int octree_locate(const DevMesh& m, const float3 q, unsigned long long& steps)
 {
     float cx = m.oroot[0], cy = m.oroot[1], cz = m.oroot[2], h = m.oroot[3];
-    int v = m.oct[0];
+    int v = gload(m.oct);
     while (v >= 0) {
         h *= 0.5f;
         const bool ux = q.x >= cx, uy = q.y >= cy, uz = q.z >= cz;
         cx = ux ? cx + h : cx - h;
         cy = uy ? cy + h : cy - h;
         cz = uz ? cz + h : cz - h;
-        v = m.oct[v + ((int)ux | ((int)uy << 1) | ((int)uz << 2))];
+        v = gload(m.oct + (v + ((int)ux | ((int)uy << 1) | ((int)uz << 2))));
         steps += 1;
     }
     return -v - 1;
@@ -356,7 +357,10 @@ constexpr int kChunk = 4;
 
 // Scans at most `budget` entries of the list of the site whose record is
 // (sp, rg); if the list is not done by then, *resume is set to the next
-// entry (else -1).
+// entry (else -1).  The first st_cnt entries' spheres are read from LDS
+// (st + st_off, staged by stage_spheres), the rest from the sphere array;
+// the two parts are scanned by separate loops so that every load has one
+// address space.
 template <bool kCtr>
 __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, const float4 sp, const int4 rg,
                                             const int budget, int* resume, QueryCounts& n, const Touch& tch,
@@ -369,30 +373,12 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
     float dmin = kInf;
     int stop = rg.w;
     *resume = -1;
-    for (int e = rg.z; e < stop; e += kChunk) {
-        if (e - rg.z >= budget) {
-            *resume = e;
-            stop = e;
-            break;
-        }
-        // the spheres (c, r) of kChunk entries, from the dense sphere array;
-        // an entry's record (a, e1, e2) is read for an exact test only
-        // (the first st_cnt of them staged in LDS at st + st_off)
-        float4 c[kChunk];
+    // Tests entries e .. e + kChunk - 1 (below `end`) given their spheres;
+    // false once the scan is over (stop set).
+    auto scan_chunk = [&](const int e, const int end, const float4 (&c)[kChunk]) -> bool {
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
-            const int idx = min(e + k, rg.w - 1);
-            const int sk = idx - rg.z;
-            if (sk < st_cnt) {
-                c[k] = st[st_off + sk];
-            } else {
-                c[k] = m.list_sph[idx];
-                if (kCtr && tch.sph) tch.sph[idx] = 1;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-            if (e + k >= stop) break;
+            if (e + k >= end) return e + k < stop;
             // Sorted by ell = |s - c| - r: no later entry can beat d_min
             // (triangle inequality).  ell is recomputed from (c, r) rather
             // than loaded, which keeps the scan to one 16-byte load per
@@ -400,20 +386,18 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
             // than the float32 rounding of the differences, the sum of
             // squares, the square root and the subtraction together, so the
             // value never exceeds the exact ell of the same float32 values
-            // by which the lists were sorted.  (Written out here: as a
-            // helper function the compiler waited for each chunk's first
-            // load before issuing the others.)
+            // by which the lists were sorted.
             const float ux = sp.x - c[k].x, uy = sp.y - c[k].y, uz = sp.z - c[k].z;
             const float ell = sqrtf(ux * ux + uy * uy + uz * uz) * (1.f - 1e-6f) - c[k].w * (1.f + 1e-6f);
             if (ell - dqs >= dmin) {
                 stop = e + k;
-                break;
+                return false;
             }
             const float dx = q.x - c[k].x, dy = q.y - c[k].y, dz = q.z - c[k].z;
             const float lim = dmin + c[k].w;
             if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) continue;
             const int64_t idx = e + k;
-            const float4 f1 = m.list_rec[3 * idx], f2 = m.list_rec[3 * idx + 1], f3 = m.list_rec[3 * idx + 2];
+            const float4 f1 = gload(m.list_rec + 3 * idx), f2 = gload(m.list_rec + 3 * idx + 1), f3 = gload(m.list_rec + 3 * idx + 2);
             if (kCtr && tch.rec) tch.rec[idx] = 1;
             float v, w;
             const float d2 = closest_point(q, make_float3(f1.x, f1.y, f1.z), make_float3(f2.x, f2.y, f2.z),
@@ -427,6 +411,34 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
                 dmin = sqrtf(d2);
             }
         }
+        return true;
+    };
+    int e = rg.z;
+    // the staged part, from LDS (all kChunk loads issued before any is used)
+    const int lds_end = rg.z + min(st_cnt, rg.w - rg.z);
+    bool more = true;
+    for (; more && e < lds_end; e += kChunk) {
+        float4 c[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) c[k] = st[st_off + min(e + k, lds_end - 1) - rg.z];
+        more = scan_chunk(e, lds_end, c);
+    }
+    // the rest, from the sphere array; an entry's record (a, e1, e2) is read
+    // for an exact test only
+    for (e = lds_end; more && e < stop; e += kChunk) {
+        if (e - rg.z >= budget) {
+            *resume = e;
+            stop = e;
+            break;
+        }
+        float4 c[kChunk];
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
+            const int idx = min(e + k, rg.w - 1);
+            c[k] = gload(m.list_sph + idx);
+            if (kCtr && tch.sph) tch.sph[idx] = 1;
+        }
+        more = scan_chunk(e, stop, c);
     }
     if (kCtr) {
         n.list_read += (unsigned long long)(stop - rg.z);
@@ -472,17 +484,27 @@ __device__ __forceinline__ float wave_min(float x)
 // each chunk; d_min is shared after every chunk, and the scan stops once
 // the chunk's last entry has ell - |q - s| >= d_min (the list is sorted by
 // ell, so no later entry can do better).  Every lane must call it.
+// Result of the wavefront's scan: the best entry and, for the instrumented
+// forward, the exact tests made and entries read.
+struct WaveScan {
+    Best b;
+    unsigned exact, read;
+};
+
 template <bool kCtr>
-__device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, const int s, const int from,
-                                              const float dmin0, unsigned long long& list_read,
-                                              unsigned long long& exact, const Touch tch)
+__device__ __noinline__ WaveScan list_search_wave(const float4* __restrict__ site_rec, const float4* __restrict__ list_sph,
+                                              const float4* __restrict__ list_rec, const float3 q, const int s,
+                                              const int from,
+                                              const float dmin0, uint8_t* __restrict__ sph_flag,
+                                              uint8_t* __restrict__ rec_flag)
 {
     const int lane = threadIdx.x & 63;
-    const float4 sp = m.site_rec[2 * s];
-    const int4 rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+    const float4 sp = gload(site_rec + 2 * s);
+    const int4 rg = __builtin_bit_cast(int4, gload(site_rec + 2 * s + 1));
     const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
     const float dqs = sqrtf(wx * wx + wy * wy + wz * wz) * 1.000001f;
     Best b{kInf, -1, 0.f, 0.f};
+    unsigned exact = 0;
     float dmin = dmin0;  // wave-uniform between chunks
     int end = rg.w;
     for (int base = from; base < rg.w; base += 64 * kWaveChunk) {
@@ -490,11 +512,11 @@ __device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, 
 #pragma unroll
         for (int k = 0; k < kWaveChunk; ++k) {
             const int idx = min(base + 64 * k + lane, rg.w - 1);
-            c[k] = m.list_sph[idx];
-            a[k] = m.list_rec[3 * (int64_t)idx];
-            if (kCtr && tch.sph) {
-                tch.sph[idx] = 1;
-                tch.rec[idx] = 1;
+            c[k] = gload(list_sph + idx);
+            a[k] = gload(list_rec + (3 * (int64_t)idx));
+            if (kCtr && sph_flag) {
+                sph_flag[idx] = 1;
+                rec_flag[idx] = 1;
             }
         }
         float dl = fminf(dmin, sqrtf(b.d2));
@@ -506,7 +528,7 @@ __device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, 
                 const float dx = q.x - c[k].x, dy = q.y - c[k].y, dz = q.z - c[k].z;
                 const float lim = dl + c[k].w;
                 if (dx * dx + dy * dy + dz * dz < lim * lim * 1.000001f) {
-                    const float4 f2 = m.list_rec[3 * (int64_t)e + 1], f3 = m.list_rec[3 * (int64_t)e + 2];
+                    const float4 f2 = gload(list_rec + (3 * (int64_t)e + 1)), f3 = gload(list_rec + (3 * (int64_t)e + 2));
                     float v, w;
                     const float d2 = closest_point(q, make_float3(a[k].x, a[k].y, a[k].z),
                                                    make_float3(f2.x, f2.y, f2.z), make_float3(f3.x, f3.y, f3.z),
@@ -518,23 +540,27 @@ __device__ __noinline__ Best list_search_wave(const DevMesh& m, const float3 q, 
                     }
                 }
             }
-            if (kCtr) exact += (unsigned long long)__popcll(__ballot(tested));
+            if (kCtr) exact += (unsigned)__popcll(__ballot(tested));
         }
         dmin = wave_min(dl);
         const int last = min(base + 64 * kWaveChunk, rg.w) - 1;
-        if (m.list_rec[3 * (int64_t)last].w - dqs >= dmin) {
+        if (gload(list_rec + (3 * (int64_t)last)).w - dqs >= dmin) {
             end = last + 1;
             break;
         }
     }
-    if (kCtr) list_read += (unsigned long long)(end - from);
-    return wave_argmin(b);
+    WaveScan r;
+    r.b = wave_argmin(b);
+    r.exact = exact;
+    r.read = (unsigned)(end - from);
+    return r;
 }
 
 // Exact branch-and-bound over the triangle BVH (points outside the domain
 // box, and walks stopped at the step cap).
 template <bool kCtr>
-__device__ Best bvh_search(const DevMesh& m, const float3 q, const Touch tch)
+__device__ __noinline__ Best bvh_search(const float4* __restrict__ bvh, const float4* __restrict__ tri_rec,
+                                        const float3 q, uint8_t* __restrict__ bvh_flag, uint8_t* __restrict__ tri_flag)
 {
     Best b{kInf, -1, 0.f, 0.f};
     int stack[64];
@@ -542,8 +568,8 @@ __device__ Best bvh_search(const DevMesh& m, const float3 q, const Touch tch)
     stack[sp++] = 0;
     while (sp > 0) {
         const int ni = stack[--sp];
-        const float4 lo = m.bvh[2 * ni], hi = m.bvh[2 * ni + 1];
-        if (kCtr && tch.bvh) tch.bvh[ni] = 1;
+        const float4 lo = gload(bvh + 2 * ni), hi = gload(bvh + 2 * ni + 1);
+        if (kCtr && bvh_flag) bvh_flag[ni] = 1;
         const float bx = fmaxf(fmaxf(lo.x - q.x, q.x - hi.x), 0.f);
         const float by = fmaxf(fmaxf(lo.y - q.y, q.y - hi.y), 0.f);
         const float bz = fmaxf(fmaxf(lo.z - q.z, q.z - hi.z), 0.f);
@@ -551,8 +577,8 @@ __device__ Best bvh_search(const DevMesh& m, const float3 q, const Touch tch)
         const int a = __float_as_int(lo.w), c = __float_as_int(hi.w);
         if (c < 0) {
             for (int slot = a; slot < a - c; ++slot) {
-                const float4* r = m.tri_rec + 3 * (int64_t)slot;
-                if (kCtr && tch.tri) tch.tri[slot] = 1;
+                const float4* r = tri_rec + 3 * (int64_t)slot;
+                if (kCtr && tri_flag) tri_flag[slot] = 1;
                 float v, w;
                 const float d2 = closest_point_rec(q, r, v, w);
                 if (d2 < b.d2) { b.d2 = d2; b.idx = -slot - 2; b.v = v; b.w = w; }
@@ -574,12 +600,20 @@ struct DirectAcc {
     float* gv;
     __device__ __forceinline__ void add(int vid, float x, float y, float z) const
     {
-        float* dst = gv + 3 * (int64_t)vid;
-        unsafeAtomicAdd(dst, x);
-        unsafeAtomicAdd(dst + 1, y);
-        unsafeAtomicAdd(dst + 2, z);
+        __attribute__((address_space(1))) float* dst = (__attribute__((address_space(1))) float*)gv + 3 * (int64_t)vid;
+        __hip_atomic_fetch_add(dst, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(dst + 1, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(dst + 2, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
+
+// An LDS pointer in LDS's own address space, so that the atomics on it are
+// issued as LDS instructions rather than flat ones.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(3))) T* lds_ptr(T* p)
+{
+    return (__attribute__((address_space(3))) T*)p;
+}
 
 struct LdsAcc {
     float* gv;
@@ -603,12 +637,16 @@ struct LdsAcc {
         uint32_t h = (uint32_t)vid * 2654435761u;
         for (int p = 0; p < kProbe; ++p) {
             const int slot = (int)((h + (uint32_t)p) & (uint32_t)(slots - 1));
-            const int prev = atomicCAS(&keys[slot], -1, vid);
-            if (prev == -1 && used) atomicAdd(used, 1);
+            int prev = -1;  // the slot's key before the exchange
+            __hip_atomic_compare_exchange_strong(lds_ptr(keys) + slot, &prev, vid, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == -1 && used)
+                __hip_atomic_fetch_add(lds_ptr(used), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (prev == -1 || prev == vid) {
-                atomicAdd(&val[3 * slot], x);
-                atomicAdd(&val[3 * slot + 1], y);
-                atomicAdd(&val[3 * slot + 2], z);
+                __attribute__((address_space(3))) float* vs = lds_ptr(val) + 3 * slot;
+                __hip_atomic_fetch_add(vs, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(vs + 1, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(vs + 2, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 return;
             }
         }
@@ -664,7 +702,7 @@ __device__ __forceinline__ void add_vertex_grads(const DevMesh& m, const Acc& ac
         }
     }
     if (head && tri >= 0) {
-        const int4 vid = m.tri_vid[tri];
+        const int4 vid = gload(m.tri_vid + tri);
         const int ids[3] = {vid.x, vid.y, vid.z};
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -701,20 +739,20 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
         const int ss = __builtin_amdgcn_readlane(s, src);
         const int from = __builtin_amdgcn_readlane(resume, src);
         const float d0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sqrtf(b.d2)), src));
-        unsigned long long lr = 0, ex = 0;
-        const Best r = list_search_wave<kCtr>(m, qs, ss, from, d0, lr, ex, tch);
+        const WaveScan r = list_search_wave<kCtr>(m.site_rec, m.list_sph, m.list_rec, qs, ss, from, d0, tch.sph,
+                                                  tch.rec);
         if ((int)(threadIdx.x & 63) == src) {
             // the lane's own result holds earlier entries and wins ties
-            if (r.d2 < b.d2) b = r;
-            list_read += lr;
-            exact += ex;
+            if (r.b.d2 < b.d2) b = r.b;
+            list_read += r.read;
+            exact += r.exact;
         }
     }
     // the fused form's gradient step below is wavefront-wide: there every
     // lane goes on
     if (!kFused && !valid) return;
     if (valid && finite && b.idx == -1) {
-        b = bvh_search<kCtr>(m, q, tch);
+        b = bvh_search<kCtr>(m.bvh, m.tri_rec, q, tch.bvh, tch.tri);
         fb = 1;
     }
     if (kCtr && valid) {
@@ -745,7 +783,7 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
     } else if (valid) {
         // the winner's caller id (from its list entry, just scanned, or the
         // fallback's slot), then its exact closest point in FP64
-        const int user = b.idx >= 0 ? __float_as_int(m.list_rec[3 * (int64_t)b.idx + 2].w) : m.tri_user[-b.idx - 2];
+        const int user = b.idx >= 0 ? __float_as_int(gload(m.list_rec + (3 * (int64_t)b.idx + 2)).w) : gload(m.tri_user + -b.idx - 2);
         const Final f = finalize(m, q, user);
         const double d = sqrt(f.d2);
         dist[i] = (float)d;
@@ -797,7 +835,7 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
                                           const Acc& acc, unsigned long long* __restrict__ ctr)
 {
     float3 q = make_float3(0.f, 0.f, 0.f);
-    if (valid) q = make_float3(qp[3 * iq], qp[3 * iq + 1], qp[3 * iq + 2]);
+    if (valid) q = make_float3(gload(qp + 3 * iq), gload(qp + 3 * iq + 1), gload(qp + 3 * iq + 2));
     const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
     QueryCounts n;
     Best b{kInf, -1, 0.f, 0.f};
@@ -810,8 +848,8 @@ __device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, co
         const Touch none{};
         if (m.oct) {
             s = octree_locate(m, q, n.steps);
-            sp = m.site_rec[2 * s];
-            rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+            sp = gload(m.site_rec + 2 * s);
+            rg = __builtin_bit_cast(int4, gload(m.site_rec + 2 * s + 1));
         } else {
             s = locate<kCtr>(m, q, n.steps, n.adj_read, n.capped, none, sp, rg);
         }
@@ -984,7 +1022,7 @@ __device__ __forceinline__ void stage_spheres(const DevMesh& m, float4* st, cons
             }
             v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
             if (src >= 0) {
-                v[u] = m.list_sph[src];
+                v[u] = gload(m.list_sph + src);
                 if (kCtr && tch.sph) tch.sph[src] = 1;
             }
         }
@@ -1007,13 +1045,16 @@ __host__ __device__ inline int search_lds_ints(int block, int stage)
     return rg > sg ? rg : sg;
 }
 
+// Seven wavefronts per SIMD (at most 72 VGPRs): measured faster than the six
+// the compiler picks by itself, its few spills being outside the list scan.
 template <bool kFused, bool kCtr>
-__global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArgs a)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) fwd_kernel(const DevMesh m,
+                                                                                             const FwdArgs a)
 {
     const int64_t per = gridDim.x / a.xcds;
     const int64_t j = xcd_block(a.xcds, per) * blockDim.x + threadIdx.x;
     const bool valid = j < a.n;
-    const int64_t i = valid ? (a.perm ? (int64_t)a.perm[j] : j) : 0;
+    const int64_t i = valid ? (a.perm ? (int64_t)gload(a.perm + j) : j) : 0;
     // The walk, then the workgroup's queries regrouped by located site (see
     // regroup_by_site), then the list scans.  LDS: the regroup's area, then
     // (fused with dL/dV) the table of vertex gradients, flushed once the
@@ -1029,7 +1070,7 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
     __syncthreads();
     const int64_t iq = a.q_sorted ? j : i;
     float3 q = make_float3(0.f, 0.f, 0.f);
-    if (valid) q = make_float3(a.q[3 * iq], a.q[3 * iq + 1], a.q[3 * iq + 2]);
+    if (valid) q = make_float3(gload(a.q + 3 * iq), gload(a.q + 3 * iq + 1), gload(a.q + 3 * iq + 2));
     const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
     int s = -1;
     float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1038,8 +1079,8 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
         unsigned long long steps = 0, adj_read = 0, capped = 0;
         if (m.oct) {
             s = octree_locate(m, q, steps);
-            sp = m.site_rec[2 * s];
-            rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+            sp = gload(m.site_rec + 2 * s);
+            rg = __builtin_bit_cast(int4, gload(m.site_rec + 2 * s + 1));
         } else {
             s = locate<kCtr>(m, q, steps, adj_read, capped, a.touch, sp, rg);
         }
@@ -1056,8 +1097,8 @@ __global__ void __launch_bounds__(1024) fwd_kernel(const DevMesh m, const FwdArg
     const bool join = __ballot(s >= 0 && rg.w - rg.z > kSerialBudget) == 0ull;
     regroup_by_site(rg_smem, nw, join, q, i2, s);
     if (s >= 0) {
-        sp = m.site_rec[2 * s];
-        rg = __builtin_bit_cast(int4, m.site_rec[2 * s + 1]);
+        sp = gload(m.site_rec + 2 * s);
+        rg = __builtin_bit_cast(int4, gload(m.site_rec + 2 * s + 1));
     }
     const bool valid2 = i2 >= 0;
     const bool finite2 = valid2 && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
@@ -1124,7 +1165,7 @@ __global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__
         for (int64_t j0 = first; j0 < last; j0 += 64) {
             const int64_t j = j0 + lane;
             const bool valid = j < last;
-            const int64_t i = valid ? base + (perm ? (int64_t)perm[j] : j) : 0;
+            const int64_t i = valid ? base + (perm ? (int64_t)gload(perm + j) : j) : 0;
             run_query<kFused, false>(m, valid, i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, acc,
                                      nullptr);
             if (kFused && gv) {

@@ -53,7 +53,7 @@ def test_c0_launch_configs_bitwise(dev, c0):
                     out = run(dev, m, c["Q"])
                     for a, b in zip(ref, out):
                         assert np.array_equal(a, b, equal_nan=True), (bs, reorder, xcd, stage)
-    m.set_query_config(block_size=256, reorder=1, xcd_groups=1, stage=1)
+    m.set_query_config(block_size=256, reorder=1, xcd_groups=1, stage=0)
 
 
 @pytest.mark.parametrize("n", [1, 4095, 4097, 300_001])
@@ -201,9 +201,9 @@ def test_c2_staging_is_exact(dev, c2):
         for stage in (0, 1):
             m.set_query_config(block_size=bs, stage=stage)
             outs[(bs, stage)] = dev.query(m, q) + dev.query_fused(m, q, g)
-    m.set_query_config(block_size=256, stage=1)
+    m.set_query_config(block_size=256, stage=0)
     torch.cuda.synchronize()
-    ref = outs[(256, 1)]
+    ref = outs[(256, 0)]
     for key, o in outs.items():
         for a, b in zip(ref, o):
             assert torch.equal(a, b), key
