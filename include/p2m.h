@@ -92,6 +92,10 @@ typedef struct {
     int32_t gpu_lists;         /* 1: the list stage's sphere-union tests run on the device
                                   (same lists; sites with more than 64 balls stay on the
                                   host); 0: all on the host (default 1; needs device >= 0) */
+    int32_t gpu_voronoi;       /* 1: the Voronoi stage's corner checks (is a site closer than
+                                  the cell's own to this corner?) run on the device, in rounds
+                                  over all cells in progress (same cells); 0: all on the host
+                                  (default 1; needs device >= 0) */
     int32_t device;            /* HIP device to upload to; -2 (default) = the current
                                   device; -1 = host only (inspection, no query calls) */
 } p2m_build_opts;
@@ -308,8 +312,11 @@ int32_t p2m_host_locate(p2m_handle h, const float* points, int64_t n, int32_t* o
 /* Batched form (not in the paper): many meshes and query sets of uneven
  * sizes in one persistent launch, captured in a HIP graph.
  *   p2m_batch_create: meshes[n_meshes] (handles outlive the batch),
- *     h_query_counts[n_meshes] (host); autotune = 1 times candidate tile and
- *     grid sizes on the first bind; cache_path (nullable) keeps the choice.
+ *     h_query_counts[n_meshes] (host); autotune = 1 times candidate launch
+ *     configurations on the first bind (see p2m_batch_config); cache_path
+ *     (nullable) keeps the choice.  Each workgroup takes work items (a tile
+ *     of one mesh's sorted queries) from a global counter and runs them
+ *     through the same search as p2m_query, regroup by site included.
  *   p2m_batch_bind: device buffers for the concatenated queries of all
  *     meshes (mesh i's points follow mesh i-1's), outputs laid out the same
  *     way; d_grad_dist nullable (forward only), else d_grad_vertices[i] is
@@ -323,8 +330,19 @@ int32_t p2m_batch_bind(p2m_batch b, const float* d_points, float* d_out_dist, in
                        float* d_out_closest, const float* d_grad_dist, float* d_grad_points,
                        float* const* d_grad_vertices, void* stream);
 int32_t p2m_batch_launch(p2m_batch b, void* stream);
-/* Chosen tile size (queries per work item) and persistent grid size. */
-int32_t p2m_batch_config(p2m_batch b, int32_t* tile, int32_t* grid, int32_t* block);
+/* The launch configuration in use (each output nullable): tile = queries
+ * per work item, grid = persistent workgroups taking items from the queue,
+ * or 0 for one workgroup per item (tile = block), block = threads per
+ * workgroup, stage = LDS staging of list spheres (0/1).  With autotune, the
+ * first bind times candidates (block 256 or 512; one workgroup per item, or
+ * items of 2, 8 or 32 blocks for 2, 4 or 8 persistent workgroups per CU;
+ * staging off or on) and keeps the fastest, cached under a key of the
+ * device and every mesh's sizes. */
+int32_t p2m_batch_config(p2m_batch b, int32_t* tile, int32_t* grid, int32_t* block, int32_t* stage);
+/* Sets the launch configuration (same meaning as p2m_batch_config's outputs;
+ * grid = 0 requires tile == block) instead of tuning; takes effect at the
+ * next p2m_batch_bind. */
+int32_t p2m_batch_set_config(p2m_batch b, int32_t tile, int32_t grid, int32_t block, int32_t stage);
 int32_t p2m_batch_destroy(p2m_batch b);
 
 const char* p2m_status_string(int32_t status);

@@ -443,9 +443,15 @@ class Batch:
         check(lib().p2m_batch_launch(self.handle, _stream(stream)))
 
     def config(self):
-        t, g, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        check(lib().p2m_batch_config(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(b)))
-        return {"tile": t.value, "grid": g.value, "block": b.value}
+        t, g, b, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().p2m_batch_config(self.handle, ctypes.byref(t), ctypes.byref(g), ctypes.byref(b),
+                                     ctypes.byref(st)))
+        return {"tile": t.value, "grid": g.value, "block": b.value, "stage": st.value}
+
+    def set_config(self, tile, grid, block, stage=0):
+        """Pin the launch configuration (see ``p2m_batch_set_config``); call
+        before ``bind``."""
+        check(lib().p2m_batch_set_config(self.handle, int(tile), int(grid), int(block), int(stage)))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -38,7 +38,8 @@ class p2m_build_opts(ctypes.Structure):
                 ("seed_cell_scale", ctypes.c_float), ("seed_max_cells", ctypes.c_int64),
                 ("n_threads", ctypes.c_int32), ("decomposition", ctypes.c_int32),
                 ("octree_max_list", ctypes.c_int32), ("octree_max_depth", ctypes.c_int32),
-                ("gpu_lists", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("gpu_lists", ctypes.c_int32), ("gpu_voronoi", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
 
 
 class p2m_stats(ctypes.Structure):
@@ -101,7 +102,8 @@ SIGNATURES = {
     "p2m_batch_bind": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "p2m_batch_launch": (_I32, [_VP, _VP]),
     "p2m_batch_config": (_I32, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
-                                ctypes.POINTER(_I32)]),
+                                ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "p2m_batch_set_config": (_I32, [_VP, _I32, _I32, _I32, _I32]),
     "p2m_batch_destroy": (_I32, [_VP]),
     "p2m_status_string": (ctypes.c_char_p, [_I32]),
     "p2m_last_error": (ctypes.c_char_p, []),

@@ -42,7 +42,8 @@ def build(verbose=False):
         objs.append(obj)
     for src in hip:
         obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
-        extra = ["-ffp-contract=off"] if os.path.basename(src) == "lists.hip" else []
+        # the preprocessing kernels reproduce the host's FP64 arithmetic exactly
+        extra = ["-ffp-contract=off"] if os.path.basename(src) in ("lists.hip", "voronoi.hip") else []
         jobs.append([HIPCC, *HIP_FLAGS, *extra, "-c", src, "-o", obj])
         objs.append(obj)
     procs = []

@@ -58,7 +58,7 @@ struct p2m_batch_ {
     int device = 0;
     int autotune = 1;
     std::string cache_path;
-    int tile = 256, grid = 0, block = 256;
+    int tile = 256, grid = 0, block = 256, stage = 0;  // one workgroup per item until tuned
     bool tuned = false;
     // device buffers
     p2m::DevMesh* d_meshes = nullptr;
@@ -140,48 +140,62 @@ struct p2m_batch_ {
         a.n_items = n_items;
         a.tile = items_tile;
         a.counter = d_counter;
-        return p2m::launch_batch(d_meshes, a, grid, block, fused, st);
+        return p2m::launch_batch(d_meshes, a, grid, block, fused, stage, st);
     }
 };
 
 namespace {
 
+// The autotuner's cache key: the device, the fused flag and every mesh's
+// triangle and query counts (a batch of other sizes gets its own entry).
 std::string cache_key(const p2m_batch_* b)
 {
-    std::ostringstream os;
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the per-mesh sizes
+    auto mix = [&](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
     int64_t tris = 0, total = 0;
     for (size_t i = 0; i < b->meshes.size(); ++i) {
         p2m_stats s;
         p2m_get_stats(b->meshes[i], &s);
         tris += s.n_triangles;
         total += b->counts[i];
+        mix((uint64_t)s.n_triangles);
+        mix((uint64_t)s.n_sites);
+        mix((uint64_t)b->counts[i]);
     }
     hipDeviceProp_t prop;
     std::string arch = "gpu";
     if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) arch = prop.gcnArchName;
-    os << arch << "_m" << b->meshes.size() << "_t" << tris << "_q" << total << "_f" << (b->fused ? 1 : 0);
+    std::ostringstream os;
+    os << arch << "_m" << b->meshes.size() << "_t" << tris << "_q" << total << "_f" << (b->fused ? 1 : 0) << "_h"
+       << std::hex << h;
     return os.str();
 }
 
-bool cache_lookup(const std::string& path, const std::string& key, int& tile, int& grid, int& block)
+bool cache_lookup(const std::string& path, const std::string& key, int& tile, int& grid, int& block, int& stage)
 {
     std::ifstream f(path);
     std::string k;
-    int t, g, bl;
-    while (f >> k >> t >> g >> bl)
+    int t, g, bl, sg;
+    while (f >> k >> t >> g >> bl >> sg)
         if (k == key) {
             tile = t;
             grid = g;
             block = bl;
+            stage = sg;
             return true;
         }
     return false;
 }
 
-void cache_store(const std::string& path, const std::string& key, int tile, int grid, int block)
+void cache_store(const std::string& path, const std::string& key, int tile, int grid, int block, int stage)
 {
     std::ofstream f(path, std::ios::app);
-    if (f) f << key << " " << tile << " " << grid << " " << block << "\n";
+    if (f) f << key << " " << tile << " " << grid << " " << block << " " << stage << "\n";
 }
 
 }  // namespace
@@ -217,7 +231,7 @@ int32_t p2m_batch_create(const p2m_handle* meshes, int32_t n_meshes, const int64
         delete b;
         return hip_fail(e, "hipGetDeviceProperties");
     }
-    b->grid = prop.multiProcessorCount * 8;
+    b->grid = 0;
     std::vector<p2m::DevMesh> dm(n_meshes);
     for (int i = 0; i < n_meshes; ++i) dm[i] = p2m::handle_devmesh(meshes[i]);
     size_t ws_total = 0;
@@ -285,15 +299,17 @@ int32_t p2m_batch_bind(p2m_batch b, const float* d_points, float* d_out_dist, in
 
     if (!b->tuned) {
         const std::string key = cache_key(b);
-        int t = b->tile, gr = b->grid, bl = b->block;
-        if (!b->cache_path.empty() && cache_lookup(b->cache_path, key, t, gr, bl)) {
+        int t = b->tile, gr = b->grid, bl = b->block, sg = b->stage;
+        if (!b->cache_path.empty() && cache_lookup(b->cache_path, key, t, gr, bl, sg)) {
             b->tile = t;
             b->grid = gr;
             b->block = bl;
+            b->stage = sg;
         } else if (b->autotune && total > 0) {
-            // Time the plain sequence for each candidate; the fused form
-            // accumulates into the caller's gradient buffers, so tune on
-            // the forward form and reuse the choice.
+            // Time the plain sequence for each candidate (work-item size,
+            // persistent workgroups per CU, workgroup size, LDS staging); the
+            // fused form accumulates into the caller's gradient buffers, so
+            // tune on the forward form and reuse the choice.
             const bool fused = b->fused;
             b->fused = false;
             hipDeviceProp_t prop;
@@ -303,38 +319,47 @@ int32_t p2m_batch_bind(p2m_batch b, const float* d_points, float* d_out_dist, in
             (void)hipEventCreate(&e0);
             (void)hipEventCreate(&e1);
             float best = 1e30f;
-            int bt = b->tile, bg = b->grid, bb = b->block;
-            for (int tile : {64, 256, 1024, 4096})
-                for (int mult : {4, 8, 16})
-                    for (int block : {256}) {
-                        int32_t rc = b->build_items(tile);
-                        if (rc != P2M_OK) return rc;
-                        b->grid = cus * mult;
-                        b->block = block;
-                        float ms = 0.f;
-                        for (int rep = 0; rep < 2; ++rep) {
-                            (void)hipEventRecord(e0, st);
-                            e = b->enqueue(st);
-                            if (e != hipSuccess) return hip_fail(e, "autotune launch");
-                            (void)hipEventRecord(e1, st);
-                            e = hipEventSynchronize(e1);
-                            if (e != hipSuccess) return hip_fail(e, "autotune sync");
-                            (void)hipEventElapsedTime(&ms, e0, e1);
+            int bt = b->tile, bg = b->grid, bb = b->block, bs = b->stage;
+            // mult 0: one workgroup per item of one block of queries (no
+            // queue); else a persistent grid of mult workgroups per CU taking
+            // items of tile_blocks blocks from the queue
+            for (int block : {256, 512})
+                for (int tile_blocks : {1, 2, 8, 32})
+                    for (int mult : {0, 2, 4, 8})
+                        for (int stage : {0, 1}) {
+                            if ((mult == 0) != (tile_blocks == 1)) continue;
+                            const int tile = tile_blocks * block;
+                            int32_t rc = b->build_items(tile);
+                            if (rc != P2M_OK) return rc;
+                            b->grid = cus * mult;
+                            b->block = block;
+                            b->stage = stage;
+                            float ms = 0.f;
+                            for (int rep = 0; rep < 2; ++rep) {
+                                (void)hipEventRecord(e0, st);
+                                e = b->enqueue(st);
+                                if (e != hipSuccess) return hip_fail(e, "autotune launch");
+                                (void)hipEventRecord(e1, st);
+                                e = hipEventSynchronize(e1);
+                                if (e != hipSuccess) return hip_fail(e, "autotune sync");
+                                (void)hipEventElapsedTime(&ms, e0, e1);
+                            }
+                            if (ms < best) {
+                                best = ms;
+                                bt = tile;
+                                bg = b->grid;
+                                bb = block;
+                                bs = stage;
+                            }
                         }
-                        if (ms < best) {
-                            best = ms;
-                            bt = tile;
-                            bg = b->grid;
-                            bb = block;
-                        }
-                    }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             b->fused = fused;
             b->tile = bt;
             b->grid = bg;
             b->block = bb;
-            if (!b->cache_path.empty()) cache_store(b->cache_path, key, bt, bg, bb);
+            b->stage = bs;
+            if (!b->cache_path.empty()) cache_store(b->cache_path, key, bt, bg, bb, bs);
         }
         b->tuned = true;
     }
@@ -380,12 +405,29 @@ int32_t p2m_batch_launch(p2m_batch b, void* stream)
     return P2M_OK;
 }
 
-int32_t p2m_batch_config(p2m_batch b, int32_t* tile, int32_t* grid, int32_t* block)
+int32_t p2m_batch_set_config(p2m_batch b, int32_t tile, int32_t grid, int32_t block, int32_t stage)
+{
+    if (!b) return fail(P2M_ERR_INVALID_ARG, "null batch");
+    if (block < 64 || block > 1024 || block % 64 != 0)
+        return fail(P2M_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+    if (grid < 0 || tile < 1 || (grid == 0 && tile != block))
+        return fail(P2M_ERR_INVALID_ARG, "tile >= 1, grid >= 0, and tile == block when grid is 0");
+    if (stage != 0 && stage != 1) return fail(P2M_ERR_INVALID_ARG, "stage must be 0 or 1");
+    b->tile = tile;
+    b->grid = grid;
+    b->block = block;
+    b->stage = stage;
+    b->tuned = true;
+    return P2M_OK;
+}
+
+int32_t p2m_batch_config(p2m_batch b, int32_t* tile, int32_t* grid, int32_t* block, int32_t* stage)
 {
     if (!b) return fail(P2M_ERR_INVALID_ARG, "null batch");
     if (tile) *tile = b->tile;
     if (grid) *grid = b->grid;
     if (block) *block = b->block;
+    if (stage) *stage = b->stage;
     return P2M_OK;
 }
 

@@ -224,6 +224,7 @@ void p2m_default_opts(p2m_build_opts* o)
     o->ring_layers = 8;
     o->aux_list_mode = 1;
     o->gpu_lists = 1;
+    o->gpu_voronoi = 1;
     o->decomposition = 0;
     o->octree_max_list = 64;
     o->octree_max_depth = 12;
@@ -259,7 +260,9 @@ int32_t p2m_build(const p2m_mesh_desc* mesh, const p2m_build_opts* opts, p2m_han
                 return fail(P2M_ERR_HIP, "cannot select HIP device " + std::to_string(dev));
             }
             const p2m::GpuListFn on_device = p2m::gpu_build_lists;
-            p2m::build_host(*mesh, o, h->H, o.gpu_lists ? &on_device : nullptr);
+            const p2m::CheckFn checks_on_device = p2m::gpu_corner_checks;
+            p2m::build_host(*mesh, o, h->H, o.gpu_lists ? &on_device : nullptr,
+                            o.gpu_voronoi ? &checks_on_device : nullptr);
             h->device = dev;
             h->upload_all(*mesh);
         } else {

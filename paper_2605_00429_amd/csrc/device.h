@@ -107,9 +107,12 @@ struct BatchArgs {
     int32_t n_items;
     int32_t tile;
     unsigned* counter;
+    int32_t stage;      // LDS staging capacity per wavefront (0: off; set by launch_batch)
+    int32_t acc_slots;  // fused: LDS hash slots for vertex gradients (set by launch_batch)
 };
 
-hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int block, bool fused,
+// stage: 1 to stage list spheres in LDS (capacity chosen here), 0 not.
+hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int block, bool fused, int stage,
                         hipStream_t st);
 hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fused, bool counters,
                           hipStream_t st);

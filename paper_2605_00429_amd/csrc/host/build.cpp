@@ -105,18 +105,26 @@ bool d3_less(const d3& a, const d3& b)
     return a.z < b.z;
 }
 
+// Per-thread scratch of the list stage.
 struct CellWork {
-    ClipCell cell;
-    std::vector<std::pair<double, int32_t>> knn;
-    std::vector<int32_t> tested, found;
-    std::vector<d3> corners, verified;
+    std::vector<d3> corners;
     std::vector<int32_t> faces;
     std::vector<Ball> balls;
     std::vector<int32_t> list;
     std::vector<uint32_t> stamp;
     uint32_t gen = 0;
-    bool unresolved = false;  // a corner check gave up (budgeted cells only)
 };
+
+// The host implementation of CheckFn.
+void host_corner_checks(const CornerChecks& job, int nth, std::vector<int32_t>& out)
+{
+    out.assign(job.q.size(), -1);
+    parallel_for((int64_t)job.q.size(), nth, [&](int64_t i, int) {
+        const int32_t l = job.list[i];
+        const int32_t* ex = job.excl.data();
+        out[i] = job.kd->below(job.q[i], job.limit2[i], ex + job.excl_off[l], ex + job.excl_off[l + 1], job.budget);
+    }, 64);
+}
 
 constexpr int kKnn = 24;
 // Sites one corner check of the first (density) pass may examine; ordinary
@@ -125,79 +133,207 @@ constexpr int64_t kPass1Budget = 4096;
 // Float32 input positions break exact co-sphericity at the 1e-7 level; a
 // violation smaller than this is rounding noise of a degenerate corner.
 constexpr double kCornerSlack = 1e-6;
+// Sites whose cells are in progress at once (bounds the memory of the
+// clipped polytopes kept between check rounds).
+constexpr int64_t kCellChunk = 32768;
 
-// Voronoi cell of site s (index into P) clipped to the box [blo, bhi].  With
-// budget >= 0 each exact corner check examines at most that many sites; a
-// check that gives up leaves the cell a superset with w.unresolved set.
-// That happens at corners that nearly all sites are almost equidistant from
-// (the centre of a sphere tessellation, the axis of a cylinder), where the
-// check would otherwise scan the whole tree.
-void voronoi_cell(int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo, d3 bhi, CellWork& w,
-                  int64_t budget = -1)
+// One cell under construction: the clipped polytope, the sites tried so far
+// (sorted; the exclusion list of its checks), the corners found final, and
+// the corners checked in the current round.
+struct CellState {
+    ClipCell cell;
+    std::vector<int32_t> tested;
+    std::vector<d3> verified, pending;
+    double dK2 = 0;
+    int64_t first = 0;  // index of its first check in the round's batch
+    bool active = false, unresolved = false;
+};
+
+// Squared distance below which a site is closer to corner x (relative to
+// the site) than the site itself, by more than the slack: a site closer
+// than s by less than kCornerSlack (relative, in squared distance) is
+// skipped, so that the cell stays a superset of the exact one; the walk's
+// stop region and the lists are both built from this computed cell.
+inline double corner_limit(d3 x) { return norm2(x) * (1.0 - kCornerSlack); }
+
+// Corners of the current polytope that still need a check: beyond half of
+// the kNN radius (closer ones cannot be cut by a site outside the kNN) and
+// not verified before.  Verified corners stay valid: clipping only removes
+// corners and adds new ones (bitwise copies survive).
+void collect_pending(CellState& c, std::vector<d3>& corners)
 {
-    const d3 ps = P[s];
-    w.unresolved = false;
-    w.cell.init_box(blo - ps, bhi - ps);
-    kd.knn(ps, kKnn, s, w.knn);
-    w.tested.clear();
-    w.tested.push_back(s);
-    double r2max = w.cell.max_norm2();
-    bool final_by_radius = false;
-    for (const auto& e : w.knn) {
-        // A site at distance >= 2 * max corner radius cannot cut the cell.
-        if (e.first >= 4.0 * r2max) {
-            final_by_radius = true;
-            break;
-        }
-        const d3 n = P[e.second] - ps;
-        if (w.cell.clip(n, 0.5 * norm2(n), e.second)) r2max = w.cell.max_norm2();
-        w.tested.push_back(e.second);
+    c.pending.clear();
+    c.cell.corners(corners);
+    for (const d3& x : corners) {
+        if (4.0 * norm2(x) <= c.dK2) continue;
+        if (std::binary_search(c.verified.begin(), c.verified.end(), x, d3_less)) continue;
+        c.pending.push_back(x);
     }
-    std::sort(w.tested.begin(), w.tested.end());
-    if (!final_by_radius && (int)w.knn.size() == kKnn) {
-        // Sites beyond the kNN radius can only cut corners farther than half
-        // of it; check those corners exactly until none is violated.
-        const double dK2 = w.knn.back().first;
-        // Corners verified once stay valid: clipping only removes corners
-        // and adds new ones (bitwise copies survive), so only new corners
-        // need the exact check.
-        w.verified.clear();
-        // Each pass finds, for every corner not yet verified, the nearest
-        // site closer to it than s (if any), then clips by all of them at
-        // once: cells with thousands of neighbours (near a rotational axis)
-        // need a few passes instead of one pass per neighbour.
-        for (size_t guard = 0; guard <= P.size(); ++guard) {
-            w.cell.corners(w.corners);
-            w.found.clear();
-            for (const d3& x : w.corners) {
-                const double r2 = norm2(x);
-                if (4.0 * r2 <= dK2) continue;
-                if (std::binary_search(w.verified.begin(), w.verified.end(), x, d3_less)) continue;
-                // A site closer than s by less than kCornerSlack (relative,
-                // in squared distance) is skipped: the cell then stays a
-                // superset of the exact one, and the walk's stop region and
-                // the lists are both built from this computed cell.
-                const int32_t f = kd.nearest_below(ps + x, r2 * (1.0 - kCornerSlack), w.tested, nullptr, false, budget);
-                if (f == -2) {
-                    w.unresolved = true;
-                    continue;
+}
+
+// Applies one round's results to a cell (results in the order of
+// c.pending): a check that gave up marks the cell unresolved, a site found
+// is clipped by, a corner with no closer site is final.  The cell stays in
+// progress, with its new corners pending, when some site was found.
+template <class Res>
+void apply_round(CellState& c, const Res& res, const std::vector<d3>& P, d3 ps, std::vector<int32_t>& found,
+                 std::vector<d3>& corners)
+{
+    found.clear();
+    for (size_t k = 0; k < c.pending.size(); ++k) {
+        const int32_t f = res(k);
+        if (f == -2) c.unresolved = true;
+        else if (f >= 0) found.push_back(f);
+        else c.verified.push_back(c.pending[k]);
+    }
+    std::sort(c.verified.begin(), c.verified.end(), d3_less);
+    if (found.empty()) {
+        c.active = false;
+        c.pending.clear();
+        return;
+    }
+    std::sort(found.begin(), found.end());
+    found.erase(std::unique(found.begin(), found.end()), found.end());
+    for (int32_t f : found) {
+        const d3 nv = P[f] - ps;
+        c.cell.clip(nv, 0.5 * norm2(nv), f);
+        c.tested.insert(std::upper_bound(c.tested.begin(), c.tested.end(), f), f);
+    }
+    collect_pending(c, corners);
+}
+
+// Cells still in progress below this count finish on the host: such a tail
+// (cells near a rotational axis that gain neighbours a few at a time) needs
+// many rounds of a few checks each, where a device round trip per round
+// costs more than the checks.
+constexpr int64_t kHostTail = 256;
+
+// Voronoi cells of the sites in `sites` (indices into P) clipped to the box
+// [blo, bhi], by rounds:
+//   1. each cell clips the box by the bisectors of its kNN in order of
+//      distance, stopping early once the next site is beyond twice the
+//      farthest corner;
+//   2. every corner that a site outside the kNN could still cut is checked
+//      (CornerChecks: the nearest site closer to it than the cell's own, or
+//      none); the checks of all cells in progress go out as one batch;
+//   3. each cell clips by the sites its checks found and collects its new
+//      corners; cells with nothing found are final.  Rounds repeat until
+//      no cell is in progress; the last few cells run their remaining
+//      rounds on the host (KdTree::below gives the same answers).
+// With budget >= 0 each check examines at most that many sites; a check
+// that gives up leaves the cell a superset and marks it unresolved.  That
+// happens at corners that nearly all sites are almost equidistant from
+// (the centre of a sphere tessellation, the axis of a cylinder).  done(i,
+// tid, corners, faces, ok, unresolved) receives sites[i]'s cell inside a
+// parallel loop.
+void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, const KdTree& kd, d3 blo, d3 bhi,
+                   int64_t budget, int nth, const CheckFn& check, bool host_tail,
+                   const std::function<void(int64_t, int, const std::vector<d3>&, const std::vector<int32_t>&, bool,
+                                            bool)>& done)
+{
+    struct Scratch {
+        std::vector<std::pair<double, int32_t>> knn;
+        std::vector<d3> corners;
+        std::vector<int32_t> found;
+        std::vector<int32_t> res;
+    };
+    std::vector<Scratch> scr(nth);
+    const int64_t n = (int64_t)sites.size();
+    if (kd.depth() + 1 > KdTree::kBelowStack) throw Error(P2M_ERR_INTERNAL, "site tree too deep");
+    for (int64_t c0 = 0; c0 < n; c0 += kCellChunk) {
+        const int64_t m = std::min(kCellChunk, n - c0);
+        std::vector<CellState> st(m);
+        parallel_for(m, nth, [&](int64_t i, int tid) {
+            CellState& c = st[i];
+            Scratch& w = scr[tid];
+            const int32_t s = sites[c0 + i];
+            const d3 ps = P[s];
+            c.cell.init_box(blo - ps, bhi - ps);
+            kd.knn(ps, kKnn, s, w.knn);
+            c.tested.push_back(s);
+            double r2max = c.cell.max_norm2();
+            bool final_by_radius = false;
+            for (const auto& e : w.knn) {
+                // a site at distance >= 2 * max corner radius cannot cut the cell
+                if (e.first >= 4.0 * r2max) {
+                    final_by_radius = true;
+                    break;
                 }
-                if (f >= 0) w.found.push_back(f);
-                else w.verified.push_back(x);
+                const d3 nv = P[e.second] - ps;
+                if (c.cell.clip(nv, 0.5 * norm2(nv), e.second)) r2max = c.cell.max_norm2();
+                c.tested.push_back(e.second);
             }
-            std::sort(w.verified.begin(), w.verified.end(), d3_less);
-            if (w.found.empty()) break;
-            std::sort(w.found.begin(), w.found.end());
-            w.found.erase(std::unique(w.found.begin(), w.found.end()), w.found.end());
-            for (int32_t f : w.found) {
-                const d3 n = P[f] - ps;
-                w.cell.clip(n, 0.5 * norm2(n), f);
-                w.tested.insert(std::upper_bound(w.tested.begin(), w.tested.end(), f), f);
+            std::sort(c.tested.begin(), c.tested.end());
+            // sites beyond the kNN radius can only cut corners farther than half of it
+            c.active = !final_by_radius && (int)w.knn.size() == kKnn;
+            if (c.active) {
+                c.dK2 = w.knn.back().first;
+                collect_pending(c, w.corners);
             }
+        }, 16);
+        std::vector<int64_t> act;
+        for (int64_t i = 0; i < m; ++i)
+            if (st[i].active) act.push_back(i);
+        for (size_t round = 0; !act.empty() && round <= P.size(); ++round) {
+            if (host_tail && (int64_t)act.size() <= kHostTail) {
+                // the tail: each cell runs its remaining rounds by itself
+                parallel_for((int64_t)act.size(), nth, [&](int64_t j, int tid) {
+                    CellState& c = st[act[j]];
+                    Scratch& w = scr[tid];
+                    const d3 ps = P[sites[c0 + act[j]]];
+                    for (size_t r = round; c.active && r <= P.size(); ++r) {
+                        w.res.resize(c.pending.size());
+                        for (size_t k = 0; k < c.pending.size(); ++k)
+                            w.res[k] = kd.below(ps + c.pending[k], corner_limit(c.pending[k]), c.tested.data(),
+                                                c.tested.data() + c.tested.size(), budget);
+                        apply_round(c, [&](size_t k) { return w.res[k]; }, P, ps, w.found, w.corners);
+                    }
+                }, 1);
+                act.clear();
+                break;
+            }
+            // one batch of checks over every cell in progress
+            CornerChecks job;
+            job.kd = &kd;
+            job.budget = budget;
+            job.excl_off.push_back(0);
+            for (int64_t i : act) {
+                CellState& c = st[i];
+                c.first = (int64_t)job.q.size();
+                const int32_t list = (int32_t)job.excl_off.size() - 1;
+                const d3 ps = P[sites[c0 + i]];
+                for (const d3& x : c.pending) {
+                    job.q.push_back(ps + x);
+                    job.limit2.push_back(corner_limit(x));
+                    job.list.push_back(list);
+                }
+                job.excl.insert(job.excl.end(), c.tested.begin(), c.tested.end());
+                job.excl_off.push_back((int64_t)job.excl.size());
+            }
+            std::vector<int32_t> res;
+            check(job, res);
+            parallel_for((int64_t)act.size(), nth, [&](int64_t j, int tid) {
+                CellState& c = st[act[j]];
+                Scratch& w = scr[tid];
+                const int64_t first = c.first;
+                apply_round(c, [&](size_t k) { return res[first + (int64_t)k]; }, P, P[sites[c0 + act[j]]], w.found,
+                            w.corners);
+            }, 16);
+            std::vector<int64_t> next;
+            for (int64_t i : act)
+                if (st[i].active) next.push_back(i);
+            act.swap(next);
         }
+        parallel_for(m, nth, [&](int64_t i, int tid) {
+            CellState& c = st[i];
+            Scratch& w = scr[tid];
+            std::vector<int32_t> faces;
+            c.cell.corners(w.corners);
+            c.cell.face_ids(faces);
+            done(c0 + i, tid, w.corners, faces, !c.cell.empty(), c.unresolved);
+            c = CellState();
+        }, 16);
     }
-    w.cell.corners(w.corners);
-    w.cell.face_ids(w.faces);
 }
 
 // Eigenvectors of a symmetric 3x3 matrix (xx, xy, xz, yy, yz, zz) by
@@ -323,7 +459,8 @@ void check_mesh(const p2m_mesh_desc& m)
 
 }  // namespace
 
-void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructure& H, const GpuListFn* gpu)
+void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructure& H, const GpuListFn* gpu,
+                const CheckFn* gpu_checks)
 {
     const auto t_start = clk::now();
     check_mesh(mesh);
@@ -411,6 +548,10 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     kd.build(P);
     std::vector<CellWork> work(nth);
     for (auto& w : work) w.stamp.assign(nT, 0);
+    const CheckFn checks = gpu_checks ? *gpu_checks
+                                      : CheckFn([nth](const CornerChecks& job, std::vector<int32_t>& out) {
+                                            host_corner_checks(job, nth, out);
+                                        });
 
     const bool octree = o.decomposition == 1;
     std::vector<char> is_aux(P.size(), 0);
@@ -461,18 +602,21 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             return ix | (iy << 21) | (iz << 42);
         };
         const double gmax = 2097150.0 * tau;
-        std::vector<std::vector<std::pair<uint64_t, d3>>> tmp(nth);
-        parallel_for(nVS, nth, [&](int64_t s, int tid) {
-            CellWork& w = work[tid];
-            voronoi_cell((int32_t)s, P, kd, blo, bhi, w, kPass1Budget);
-            cell_corners[s] = w.corners;
-            cell_faces[s] = w.faces;
-            cell_ok[s] = !w.cell.empty();
-            unresolved[s] = w.unresolved;
+        // Voronoi vertices of each cell that can seed a cluster, keyed by
+        // their grid cell (sorted by key within the site)
+        std::vector<std::vector<std::pair<uint64_t, d3>>> site_keys(nVS);
+        std::vector<int32_t> vsites(nVS);
+        std::iota(vsites.begin(), vsites.end(), 0);
+        compute_cells(vsites, P, kd, blo, bhi, kPass1Budget, nth, checks, gpu_checks != nullptr,
+                      [&](int64_t s, int, const std::vector<d3>& corners, const std::vector<int32_t>& faces, bool ok,
+                          bool unres) {
+            cell_corners[s] = corners;
+            cell_faces[s] = faces;
+            cell_ok[s] = ok;
+            unresolved[s] = unres;
             const d3 ps = P[s];
-            auto& kc = tmp[tid];
-            kc.clear();
-            for (const d3& x : w.corners) {
+            auto& kc = site_keys[s];
+            for (const d3& x : corners) {
                 const d3 u = ps + x;
                 // finite Voronoi vertices only (not on the domain box)
                 if (u.x <= blo.x + tolb || u.y <= blo.y + tolb || u.z <= blo.z + tolb ||
@@ -484,12 +628,36 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
                 if (u.x - glo.x > gmax || u.y - glo.y > gmax || u.z - glo.z > gmax) continue;
                 kc.push_back({key_of(u), u});
             }
-            std::sort(kc.begin(), kc.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
-            for (size_t i = 0; i < kc.size(); ++i) {
-                Acc& a = maps[tid][kc[i].first];
-                if (i == 0 || kc[i].first != kc[i - 1].first) a.n++;
+            std::stable_sort(kc.begin(), kc.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        });
+        // Per grid cell: distinct sites, vertex count and moments, summed in
+        // site order (so that the sums do not depend on the thread count or
+        // scheduling): the keys are split into buckets by value, each bucket
+        // gathered in site order and summed by one thread.
+        const int nb = std::max(1, nth) * 4;
+        std::vector<std::vector<std::pair<uint64_t, d3>>> buckets(nb);
+        std::vector<std::vector<int32_t>> bucket_site(nb);
+        for (int32_t s = 0; s < nVS; ++s) {
+            for (const auto& kv : site_keys[s]) {
+                const int b = (int)((kv.first * 0x9E3779B97F4A7C15ull) >> 58) % nb;
+                buckets[b].push_back(kv);
+                bucket_site[b].push_back(s);
+            }
+            std::vector<std::pair<uint64_t, d3>>().swap(site_keys[s]);
+        }
+        parallel_for(nb, nth, [&](int64_t b, int tid) {
+            auto& e = buckets[b];
+            auto& es = bucket_site[b];
+            std::vector<int64_t> ord(e.size());
+            std::iota(ord.begin(), ord.end(), 0);
+            std::stable_sort(ord.begin(), ord.end(), [&](int64_t i, int64_t j) { return e[i].first < e[j].first; });
+            auto& mp = maps[tid];
+            for (size_t k = 0; k < ord.size(); ++k) {
+                const int64_t i = ord[k];
+                Acc& a = mp[e[i].first];
+                if (k == 0 || e[i].first != e[ord[k - 1]].first || es[i] != es[ord[k - 1]]) a.n++;
                 a.nc++;
-                const d3 u = kc[i].second;
+                const d3 u = e[i].second;
                 a.s = a.s + u;
                 a.s2 += norm2(u);
                 a.m[0] += u.x * u.x;
@@ -499,16 +667,11 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
                 a.m[4] += u.y * u.z;
                 a.m[5] += u.z * u.z;
             }
-        });
+        }, 1);
+        // each key lives in one bucket, so merging the per-thread maps only
+        // moves entries
         for (int t = 1; t < nth; ++t)
-            for (auto& kv : maps[t]) {
-                Acc& a = maps[0][kv.first];
-                a.n += kv.second.n;
-                a.nc += kv.second.nc;
-                a.s = a.s + kv.second.s;
-                a.s2 += kv.second.s2;
-                for (int k = 0; k < 6; ++k) a.m[k] += kv.second.m[k];
-            }
+            for (auto& kv : maps[t]) maps[0][kv.first] = kv.second;
         t_vor1 = secs_since(t0);
         // Reference density: grid cells that hold mesh vertices (the
         // sampling density near the surface the paper scales tau by).
@@ -626,11 +789,13 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
                 KdTree kd2;
                 kd2.build(PP);
                 std::vector<char> drop(aux.size(), 0);
-                parallel_for((int64_t)aux.size(), nth, [&](int64_t i, int tid) {
-                    CellWork& w = work[tid];
-                    voronoi_cell((int32_t)(nVS + i), PP, kd2, blo, bhi, w);
-                    if (w.faces.empty() || w.faces.front() < 0 || w.cell.empty()) drop[i] = 1;
-                }, 8);
+                std::vector<int32_t> asites(aux.size());
+                std::iota(asites.begin(), asites.end(), nVS);
+                compute_cells(asites, PP, kd2, blo, bhi, -1, nth, checks, gpu_checks != nullptr,
+                              [&](int64_t i, int, const std::vector<d3>&, const std::vector<int32_t>& faces, bool ok,
+                                  bool) {
+                    if (faces.empty() || faces.front() < 0 || !ok) drop[i] = 1;
+                });
                 std::vector<d3> keep;
                 for (size_t i = 0; i < aux.size(); ++i)
                     if (!drop[i]) keep.push_back(aux[i]);
@@ -669,14 +834,19 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     cell_faces.resize(nS);
     cell_ok.resize(nS, 0);
     cell_done.resize(nS, 0);
-    parallel_for(nS, nth, [&](int64_t s, int tid) {
-        if (cell_done[s]) return;
-        CellWork& w = work[tid];
-        voronoi_cell((int32_t)s, P, kd, blo, bhi, w);
-        cell_corners[s] = w.corners;
-        cell_faces[s] = w.faces;
-        cell_ok[s] = !w.cell.empty();
-    }, 16);
+    {
+        std::vector<int32_t> todo;
+        for (int32_t s = 0; s < nS; ++s)
+            if (!cell_done[s]) todo.push_back(s);
+        compute_cells(todo, P, kd, blo, bhi, -1, nth, checks, gpu_checks != nullptr,
+                      [&](int64_t i, int, const std::vector<d3>& corners, const std::vector<int32_t>& faces, bool ok,
+                          bool) {
+            const int32_t s = todo[i];
+            cell_corners[s] = corners;
+            cell_faces[s] = faces;
+            cell_ok[s] = ok;
+        });
+    }
     H.stats.t_voronoi_s = t_vor1 + secs_since(t0);
     t0 = clk::now();
     nbr.assign(nS, {});
@@ -947,11 +1117,33 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         }
         H.seed.resize(ncell);
         const double gc = (double)H.gcell;
-        parallel_for(ncell, nth, [&](int64_t idx, int) {
+        auto centre = [&](int64_t idx) {
             const int64_t ix = idx % g[0], iy = (idx / g[0]) % g[1], iz = idx / (g[0] * g[1]);
-            const d3 c{H.gorg[0] + (ix + 0.5) * gc, H.gorg[1] + (iy + 0.5) * gc, H.gorg[2] + (iz + 0.5) * gc};
-            H.seed[idx] = new_id[kd.nearest(c)];
-        }, 1024);
+            return d3{H.gorg[0] + (ix + 0.5) * gc, H.gorg[1] + (iy + 0.5) * gc, H.gorg[2] + (iz + 0.5) * gc};
+        };
+        if (gpu_checks) {
+            // the nearest site is the corner check with no limit and nothing
+            // excluded (the same search as KdTree::nearest), in slices
+            const int64_t slice = int64_t(1) << 22;
+            for (int64_t b = 0; b < ncell; b += slice) {
+                const int64_t m = std::min(slice, ncell - b);
+                CornerChecks job;
+                job.kd = &kd;
+                job.q.resize(m);
+                parallel_for(m, nth, [&](int64_t i, int) { job.q[i] = centre(b + i); }, 4096);
+                job.limit2.assign(m, INFINITY);
+                job.list.assign(m, 0);
+                job.excl_off.assign(2, 0);
+                std::vector<int32_t> res;
+                (*gpu_checks)(job, res);
+                for (int64_t i = 0; i < m; ++i) {
+                    if (res[i] < 0) throw Error(P2M_ERR_INTERNAL, "device nearest-site search found no site");
+                    H.seed[b + i] = new_id[res[i]];
+                }
+            }
+        } else {
+            parallel_for(ncell, nth, [&](int64_t idx, int) { H.seed[idx] = new_id[kd.nearest(centre(idx))]; }, 1024);
+        }
     }
     H.stats.t_layout_s = secs_since(t0);
 

@@ -84,11 +84,34 @@ struct GpuListJob {
 using GpuListFn = std::function<void(const GpuListJob&, std::vector<int64_t>& off, std::vector<int32_t>& ids,
                                      std::vector<char>& redo)>;
 
+class KdTree;
+
+// A batch of corner checks of the Voronoi stage against the sites of one
+// kd-tree: for check i, KdTree::below(q[i], limit2[i], exclusion list
+// list[i], budget), where exclusion list j is the sorted run
+// excl[excl_off[j] .. excl_off[j + 1]).
+struct CornerChecks {
+    const KdTree* kd = nullptr;
+    std::vector<d3> q;
+    std::vector<double> limit2;
+    std::vector<int32_t> list;
+    std::vector<int64_t> excl_off;
+    std::vector<int32_t> excl;
+    int64_t budget = -1;
+};
+// Fills out[i] with check i's result (site index, -1 or -2).  Throws
+// p2m::Error.
+using CheckFn = std::function<void(const CornerChecks&, std::vector<int32_t>& out)>;
+
 // Throws p2m::Error on invalid input.  With `gpu`, the list stage's
 // sphere-union tests run through it (sites with more than 64 balls stay on
-// the host); the lists are the same.
+// the host); with `gpu_checks`, the Voronoi stage's corner checks do.  The
+// structure is the same either way.
 void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& opts, HostStructure& out,
-                const GpuListFn* gpu = nullptr);
+                const GpuListFn* gpu = nullptr, const CheckFn* gpu_checks = nullptr);
+
+// The device implementation of CheckFn (current HIP device).
+void gpu_corner_checks(const CornerChecks& job, std::vector<int32_t>& out);
 
 // The device implementation of GpuListFn (current HIP device).
 void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vector<int32_t>& ids,

@@ -1,6 +1,7 @@
 #include "kdtree.h"
 
 #include <algorithm>
+#include <atomic>
 #include <limits>
 #include <queue>
 
@@ -12,16 +13,20 @@ constexpr int kLeaf = 8;
 
 void KdTree::build(const std::vector<d3>& pts)
 {
+    static std::atomic<uint64_t> next_stamp{1};
+    stamp_ = next_stamp.fetch_add(1);
     pts_ = pts;
     idx_.resize(pts.size());
     for (size_t i = 0; i < pts.size(); ++i) idx_[i] = (int32_t)i;
     nodes_.clear();
     nodes_.reserve(2 * pts.size() / kLeaf + 2);
-    if (!pts.empty()) build_rec(0, (int32_t)pts.size());
+    depth_ = 0;
+    if (!pts.empty()) build_rec(0, (int32_t)pts.size(), 1);
 }
 
-int32_t KdTree::build_rec(int32_t b, int32_t e)
+int32_t KdTree::build_rec(int32_t b, int32_t e, int depth)
 {
+    depth_ = std::max(depth_, depth);
     Node n;
     n.lo = {INFINITY, INFINITY, INFINITY};
     n.hi = {-INFINITY, -INFINITY, -INFINITY};
@@ -40,8 +45,8 @@ int32_t KdTree::build_rec(int32_t b, int32_t e)
     int32_t m = b + (e - b) / 2;
     std::nth_element(idx_.begin() + b, idx_.begin() + m, idx_.begin() + e,
                      [&](int32_t i, int32_t j) { return comp(pts_[i], axis) < comp(pts_[j], axis); });
-    int32_t l = build_rec(b, m);
-    int32_t r = build_rec(m, e);
+    int32_t l = build_rec(b, m, depth + 1);
+    int32_t r = build_rec(m, e, depth + 1);
     nodes_[id].left = l;
     nodes_[id].right = r;
     return id;
@@ -144,6 +149,71 @@ int32_t KdTree::nearest_below(d3 q, double limit2, const std::vector<int32_t>& e
     }
     if (d2_out) *d2_out = best;
     return bi;
+}
+
+int32_t KdTree::below(d3 q, double limit2, const int32_t* ex_begin, const int32_t* ex_end, int64_t budget) const
+{
+    if (nodes_.empty()) return -1;
+    double best = limit2;
+    int32_t bi = -1;
+    struct Item { double d2; int32_t node; };
+    // a depth-first search keeps at most one pending sibling per level
+    Item st[kBelowStack];
+    int top = 0;
+    st[top++] = {box_d2(nodes_[0], q), 0};
+    while (top > 0) {
+        const Item it = st[--top];
+        if (it.d2 >= best) continue;
+        const Node& n = nodes_[it.node];
+        if (n.left < 0) {
+            if (budget >= 0) {
+                budget -= n.end - n.begin;
+                if (budget < 0) return -2;
+            }
+            for (int32_t i = n.begin; i < n.end; ++i) {
+                const int32_t p = idx_[i];
+                const double d2 = norm2(pts_[p] - q);
+                if (d2 < best || (d2 == best && bi >= 0 && p < bi)) {
+                    if (std::binary_search(ex_begin, ex_end, p)) continue;
+                    best = d2;
+                    bi = p;
+                }
+            }
+            continue;
+        }
+        const double dl = box_d2(nodes_[n.left], q), dr = box_d2(nodes_[n.right], q);
+        if (dl <= dr) {
+            st[top++] = {dr, n.right};
+            st[top++] = {dl, n.left};
+        } else {
+            st[top++] = {dl, n.left};
+            st[top++] = {dr, n.right};
+        }
+    }
+    return bi;
+}
+
+void KdTree::export_flat(std::vector<double>& box, std::vector<int32_t>& link, std::vector<int32_t>& order,
+                         std::vector<double>& pts) const
+{
+    box.resize(6 * nodes_.size());
+    link.resize(4 * nodes_.size());
+    for (size_t i = 0; i < nodes_.size(); ++i) {
+        const Node& n = nodes_[i];
+        const double b[6] = {n.lo.x, n.lo.y, n.lo.z, n.hi.x, n.hi.y, n.hi.z};
+        std::copy(b, b + 6, box.begin() + 6 * i);
+        link[4 * i] = n.begin;
+        link[4 * i + 1] = n.end;
+        link[4 * i + 2] = n.left;
+        link[4 * i + 3] = n.right;
+    }
+    order = idx_;
+    pts.resize(3 * pts_.size());
+    for (size_t i = 0; i < pts_.size(); ++i) {
+        pts[3 * i] = pts_[i].x;
+        pts[3 * i + 1] = pts_[i].y;
+        pts[3 * i + 2] = pts_[i].z;
+    }
 }
 
 int32_t KdTree::nearest(d3 q, double* d2_out) const

@@ -22,6 +22,15 @@ public:
     // points and returns -2 (undecided).
     int32_t nearest_below(d3 q, double limit2, const std::vector<int32_t>& excluded,
                           double* d2_out = nullptr, bool first = false, int64_t max_points = -1) const;
+    // nearest_below(q, limit2, excluded, nullptr, false, budget) with the
+    // excluded indices given as a sorted range; the search order (nearer
+    // child first) and the budget count are the same, which a device
+    // version reproduces step for step.
+    int32_t below(d3 q, double limit2, const int32_t* ex_begin, const int32_t* ex_end, int64_t budget = -1) const;
+    // Levels of the tree (its nodes' deepest level, root = 1).  A
+    // depth-first search of it holds at most depth + 1 entries.
+    int depth() const { return depth_; }
+    static constexpr int kBelowStack = 64;
     // Exact nearest point (lowest index on exact ties).
     int32_t nearest(d3 q, double* d2_out = nullptr) const;
     // Every point with squared distance <= r2 (appended, unordered).
@@ -29,17 +38,29 @@ public:
     // Points in tree order (a spatially coherent permutation).
     const std::vector<int32_t>& order() const { return idx_; }
 
+    // Flat copy for a device: per node lo.xyz, hi.xyz (6 doubles) and
+    // begin, end, left, right (4 ints; left = -1 for a leaf); the point
+    // order; the points (3 doubles each).
+    void export_flat(std::vector<double>& box, std::vector<int32_t>& link, std::vector<int32_t>& order,
+                     std::vector<double>& pts) const;
+    int32_t n_nodes() const { return (int32_t)nodes_.size(); }
+    // Distinct for every build of any tree in the process (a device copy
+    // made from one build can be reused until the tree is rebuilt).
+    uint64_t stamp() const { return stamp_; }
+
 private:
     struct Node {
         d3 lo, hi;
         int32_t begin, end;   // range in idx_ (leaves)
         int32_t left, right;  // children, -1 for a leaf
     };
-    int32_t build_rec(int32_t b, int32_t e);
+    int32_t build_rec(int32_t b, int32_t e, int depth);
     static double box_d2(const Node& n, d3 q);
     std::vector<d3> pts_;
     std::vector<int32_t> idx_;
     std::vector<Node> nodes_;
+    int depth_ = 0;
+    uint64_t stamp_ = 0;
 };
 
 }  // namespace p2m

@@ -823,42 +823,6 @@ __device__ __forceinline__ void finish_query(const DevMesh& m, const bool valid,
     if (kFused && acc.gv) add_vertex_grads(m, acc, gtri, gc);
 }
 
-// One query end to end: the point read at iq (its slot in qp), located by
-// the walk (or the octree descent), then finish_query with outputs at i.
-// Shared by the fused and the batched kernels.  Every lane of the wavefront
-// must call it.
-template <bool kFused, bool kCtr, class Acc>
-__device__ __forceinline__ void run_query(const DevMesh& m, const bool valid, const int64_t iq, const int64_t i,
-                                          const float* __restrict__ qp, float* __restrict__ dist,
-                                          int32_t* __restrict__ tri, float* __restrict__ closest,
-                                          const float* __restrict__ gdist, float* __restrict__ grad_q,
-                                          const Acc& acc, unsigned long long* __restrict__ ctr)
-{
-    float3 q = make_float3(0.f, 0.f, 0.f);
-    if (valid) q = make_float3(gload(qp + 3 * iq), gload(qp + 3 * iq + 1), gload(qp + 3 * iq + 2));
-    const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
-    QueryCounts n;
-    Best b{kInf, -1, 0.f, 0.f};
-    int s = -1, resume = -1;
-    if (finite && in_domain(m, q)) {
-        // the site's record (position, adjacency and list ranges): the walk
-        // has just read it
-        float4 sp;
-        int4 rg;
-        const Touch none{};
-        if (m.oct) {
-            s = octree_locate(m, q, n.steps);
-            sp = gload(m.site_rec + 2 * s);
-            rg = __builtin_bit_cast(int4, gload(m.site_rec + 2 * s + 1));
-        } else {
-            s = locate<kCtr>(m, q, n.steps, n.adj_read, n.capped, none, sp, rg);
-        }
-        if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n, none);
-    }
-    finish_query<kFused, kCtr>(m, valid, q, finite, s, b, resume, i, dist, tri, closest, gdist, grad_q, acc, ctr,
-                               n, Touch{});
-}
-
 // Regroups a workgroup's queries by located site, so that lanes holding
 // the same site become neighbours: the list scans of a wavefront then read
 // the same entries, one cache line serving many lanes, instead of a few
@@ -968,14 +932,15 @@ __device__ __forceinline__ int64_t xcd_block(const int xcds, const int64_t per)
 // LDS staging of the list spheres a wavefront is about to scan (the
 // "List Search" of Sec. 3.4 reading its candidates from LDS).  After the
 // regroup, lanes holding one site are neighbours; each distinct site of the
-// wavefront gets the first entries of its list copied into the wavefront's
-// kStageEntries-entry area, whole 16-byte spheres, 64 consecutive entries
-// per load instruction, so that one coalesced load serves what 64 per-lane
-// gathers of the scan would have read.  Sites are taken in the order of
-// their first lane until the area (cap entries) is full; a lane's st_off
-// / st_cnt give where its list's first st_cnt entries are (st_cnt = 0: none
-// staged).  Every lane of the wavefront must call it.
+// wavefront held by at least kStageMinLanes lanes gets the first entries of
+// its list copied into the wavefront's area (cap entries), its lanes
+// copying entries rank, rank + lanes, ... so that each load instruction
+// reads consecutive spheres.  Sites are taken in the order of their first
+// lane until the area is full; a lane's st_off / st_cnt give where its
+// list's first st_cnt entries are (st_cnt = 0: none staged).  Every lane of
+// the wavefront must call it.
 constexpr int kStageEntries = 256;  // largest area per wavefront
+constexpr int kStageMinLanes = 4;
 constexpr int kStageUnroll = 4;
 
 template <bool kCtr>
@@ -983,52 +948,39 @@ __device__ __forceinline__ void stage_spheres(const DevMesh& m, float4* st, cons
                                               const int4 rg, int& st_off, int& st_cnt, const Touch& tch)
 {
     const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     st_off = 0;
     st_cnt = 0;
-    // the distinct sites: lane g keeps group g's first entry, offset, count
-    int g_first = 0, g_off = 0, g_cnt = 0;
-    int ng = 0, total = 0;
+    int rank = 0, lanes = 1, total = 0;
     for (uint64_t todo = __ballot(s >= 0); todo;) {
         const int lead = __builtin_ctzll(todo);
         const int ls = __builtin_amdgcn_readlane(s, lead);
         const bool mine = s == ls;
-        todo &= ~__ballot(mine);
-        const int lb = __builtin_amdgcn_readlane(rg.z, lead);
-        const int cnt = min(__builtin_amdgcn_readlane(rg.w, lead) - lb, cap - total);
+        const uint64_t grp = __ballot(mine);
+        todo &= ~grp;
+        const int n_lanes = __popcll(grp);
+        if (n_lanes < kStageMinLanes) continue;
+        const int len = __builtin_amdgcn_readlane(rg.w - rg.z, lead);
+        const int cnt = min(len, cap - total);
         if (mine) {
             st_off = total;
             st_cnt = cnt;
+            rank = __popcll(grp & below);
+            lanes = n_lanes;
         }
-        if (lane == ng) {
-            g_first = lb;
-            g_off = total;
-            g_cnt = cnt;
-        }
-        ++ng;
         total += cnt;
     }
-    // flat staged entry f = j + 64 u + lane comes from the group holding it
-    for (int j = 0; j < total; j += 64 * kStageUnroll) {
+    for (int k0 = rank; k0 < st_cnt; k0 += lanes * kStageUnroll) {
         float4 v[kStageUnroll];
-        int f[kStageUnroll];
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u) {
-            f[u] = j + 64 * u + lane;
-            int src = -1;
-            for (int g = 0; g < ng; ++g) {
-                const int go = __builtin_amdgcn_readlane(g_off, g);
-                const int gc = __builtin_amdgcn_readlane(g_cnt, g);
-                if (f[u] >= go && f[u] < go + gc) src = __builtin_amdgcn_readlane(g_first, g) + (f[u] - go);
-            }
-            v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (src >= 0) {
-                v[u] = gload(m.list_sph + src);
-                if (kCtr && tch.sph) tch.sph[src] = 1;
-            }
+            const int k = min(k0 + u * lanes, st_cnt - 1);
+            v[u] = gload(m.list_sph + rg.z + k);
+            if (kCtr && tch.sph) tch.sph[rg.z + k] = 1;
         }
 #pragma unroll
         for (int u = 0; u < kStageUnroll; ++u)
-            if (f[u] < total) st[f[u]] = v[u];
+            if (k0 + u * lanes < st_cnt) st[st_off + k0 + u * lanes] = v[u];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1045,32 +997,33 @@ __host__ __device__ inline int search_lds_ints(int block, int stage)
     return rg > sg ? rg : sg;
 }
 
-// Seven wavefronts per SIMD (at most 72 VGPRs): measured faster than the six
-// the compiler picks by itself, its few spills being outside the list scan.
+// Where one workgroup's tile of queries comes from and goes to: point j of
+// the tile (thread j) is read at q[3 iq] and its outputs written at i.
+struct TileIo {
+    const float* q;
+    float* dist;
+    int32_t* tri;
+    float* closest;
+    const float* grad_dist;
+    float* grad_q;
+    unsigned long long* ctr;
+    Touch touch;
+    int stage;
+};
+
+// One workgroup's tile of queries through the whole search: the walk, the
+// queries regrouped by located site (see regroup_by_site), optionally the
+// located sites' spheres staged in LDS, the list scans and the outputs.
+// smem starts with the regroup's area (nw * 256 counts, zeroed by the caller
+// before a barrier, then the slots), which the staging area reuses.  Every
+// thread of the workgroup must call it.
 template <bool kFused, bool kCtr>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) fwd_kernel(const DevMesh m,
-                                                                                             const FwdArgs a)
+__device__ __forceinline__ void search_tile(const DevMesh& m, int* smem, const TileIo& io, const LdsAcc& acc,
+                                            const bool valid, const int64_t i, const int64_t iq)
 {
-    const int64_t per = gridDim.x / a.xcds;
-    const int64_t j = xcd_block(a.xcds, per) * blockDim.x + threadIdx.x;
-    const bool valid = j < a.n;
-    const int64_t i = valid ? (a.perm ? (int64_t)gload(a.perm + j) : j) : 0;
-    // The walk, then the workgroup's queries regrouped by located site (see
-    // regroup_by_site), then the list scans.  LDS: the regroup's area, then
-    // (fused with dL/dV) the table of vertex gradients, flushed once the
-    // workgroup is done.
-    extern __shared__ __align__(16) int smem[];
     const int nw = (int)(blockDim.x >> 6);
-    int* rg_smem = smem;
-    int* acc_smem = smem + search_lds_ints((int)blockDim.x, a.stage);
-    const bool gv = kFused && a.grad_v;
-    const LdsAcc acc{gv ? a.grad_v : nullptr, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
-    for (int k = threadIdx.x; k < nw * 256; k += blockDim.x) rg_smem[k] = 0;
-    if (gv) acc.init();
-    __syncthreads();
-    const int64_t iq = a.q_sorted ? j : i;
     float3 q = make_float3(0.f, 0.f, 0.f);
-    if (valid) q = make_float3(gload(a.q + 3 * iq), gload(a.q + 3 * iq + 1), gload(a.q + 3 * iq + 2));
+    if (valid) q = make_float3(gload(io.q + 3 * iq), gload(io.q + 3 * iq + 1), gload(io.q + 3 * iq + 2));
     const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
     int s = -1;
     float4 sp = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1082,12 +1035,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8)
             sp = gload(m.site_rec + 2 * s);
             rg = __builtin_bit_cast(int4, gload(m.site_rec + 2 * s + 1));
         } else {
-            s = locate<kCtr>(m, q, steps, adj_read, capped, a.touch, sp, rg);
+            s = locate<kCtr>(m, q, steps, adj_read, capped, io.touch, sp, rg);
         }
         if (kCtr) {
-            atomicAdd(&a.ctr[CTR_WALK_STEPS], steps);
-            atomicAdd(&a.ctr[CTR_ADJ_READ], adj_read);
-            atomicAdd(&a.ctr[CTR_WALK_CAP], capped);
+            atomicAdd(&io.ctr[CTR_WALK_STEPS], steps);
+            atomicAdd(&io.ctr[CTR_ADJ_READ], adj_read);
+            atomicAdd(&io.ctr[CTR_WALK_CAP], capped);
         }
     }
     // Wavefronts holding a list longer than one lane's scan budget keep
@@ -1095,7 +1048,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8)
     // themselves.
     int64_t i2 = valid ? i : -1;
     const bool join = __ballot(s >= 0 && rg.w - rg.z > kSerialBudget) == 0ull;
-    regroup_by_site(rg_smem, nw, join, q, i2, s);
+    regroup_by_site(smem, nw, join, q, i2, s);
     if (s >= 0) {
         sp = gload(m.site_rec + 2 * s);
         rg = __builtin_bit_cast(int4, gload(m.site_rec + 2 * s + 1));
@@ -1105,86 +1058,128 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8)
     // the located sites' spheres staged in LDS (the area reuses the
     // regroup's, once every wavefront has read its slot back)
     int st_off = 0, st_cnt = 0;
-    float4* st = (float4*)smem + (threadIdx.x >> 6) * a.stage;
-    if (a.stage > 0) {
+    float4* st = (float4*)smem + (threadIdx.x >> 6) * io.stage;
+    if (io.stage > 0) {
         __syncthreads();
-        stage_spheres<kCtr>(m, st, a.stage, s, rg, st_off, st_cnt, a.touch);
+        stage_spheres<kCtr>(m, st, io.stage, s, rg, st_off, st_cnt, io.touch);
     }
     QueryCounts n;
     Best b{kInf, -1, 0.f, 0.f};
     int resume = -1;
-    if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n, a.touch, st, st_off, st_cnt);
-    finish_query<kFused, kCtr>(m, valid2, q, finite2, s, b, resume, valid2 ? i2 : 0, a.dist, a.tri, a.closest,
-                               a.grad_dist, a.grad_q, acc, a.ctr, n, a.touch);
+    if (s >= 0) b = list_search<kCtr>(m, q, sp, rg, kSerialBudget, &resume, n, io.touch, st, st_off, st_cnt);
+    finish_query<kFused, kCtr>(m, valid2, q, finite2, s, b, resume, valid2 ? i2 : 0, io.dist, io.tri, io.closest,
+                               io.grad_dist, io.grad_q, acc, io.ctr, n, io.touch);
+}
+
+// Seven wavefronts per SIMD (at most 72 VGPRs): measured faster than the six
+// the compiler picks by itself, its few spills being outside the list scan.
+template <bool kFused, bool kCtr>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) fwd_kernel(const DevMesh m,
+                                                                                             const FwdArgs a)
+{
+    const int64_t per = gridDim.x / a.xcds;
+    const int64_t j = xcd_block(a.xcds, per) * blockDim.x + threadIdx.x;
+    const bool valid = j < a.n;
+    const int64_t i = valid ? (a.perm ? (int64_t)gload(a.perm + j) : j) : 0;
+    // LDS: the search's area (regroup, staging), then (fused with dL/dV) the
+    // table of vertex gradients, flushed once the workgroup is done.
+    extern __shared__ __align__(16) int smem[];
+    const int nw = (int)(blockDim.x >> 6);
+    int* acc_smem = smem + search_lds_ints((int)blockDim.x, a.stage);
+    const bool gv = kFused && a.grad_v;
+    const LdsAcc acc{gv ? a.grad_v : nullptr, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
+    for (int k = threadIdx.x; k < nw * 256; k += blockDim.x) smem[k] = 0;
+    if (gv) acc.init();
+    __syncthreads();
+    const TileIo io{a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, a.ctr, a.touch, a.stage};
+    search_tile<kFused, kCtr>(m, smem, io, acc, valid, i, a.q_sorted ? j : i);
     if (gv) {
         __syncthreads();
         acc.flush();
     }
 }
 
-// Persistent batched kernel: each wavefront takes work items (up to `tile`
+// Persistent batched kernel: each workgroup takes work items (up to `tile`
 // consecutive sorted queries of one mesh) from a global counter until none
-// is left, so meshes of very different sizes share one launch.  Fused, each
-// wavefront combines the vertex gradients of its 64 queries in its own LDS
-// hash table (kWaveSlots slots, at least 4/3 of the 192 contributions) and
-// flushes it to the current mesh's dL/dV after every round of 64.
-constexpr int kWaveSlots = 256;
-
+// is left, so meshes of very different sizes share one launch, and runs
+// each item's queries through search_tile blockDim at a time (the walk, the
+// regroup by site, the scans), as the plain kernel does for its one tile.
+// Fused, the workgroup's LDS table of vertex gradients is flushed to the
+// item's mesh after every item.
 template <bool kFused>
-__global__ void __launch_bounds__(1024) batch_kernel(const DevMesh* __restrict__ meshes, const BatchArgs a)
+__global__ void __launch_bounds__(1024) batch_kernel(
+    const DevMesh* __restrict__ meshes, const BatchArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    extern __shared__ int wave_smem[];
-    int* wkeys = wave_smem + (threadIdx.x >> 6) * (4 * kWaveSlots);
-    float* wval = (float*)(wkeys + kWaveSlots);
-    if (kFused) {
-        for (int k = lane; k < kWaveSlots; k += 64) {
-            wkeys[k] = -1;
-            wval[3 * k] = 0.f;
-            wval[3 * k + 1] = 0.f;
-            wval[3 * k + 2] = 0.f;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
+    extern __shared__ __align__(16) int smem[];
+    __shared__ unsigned item_sh;
+    const int nw = (int)(blockDim.x >> 6);
+    int* acc_smem = smem + search_lds_ints((int)blockDim.x, a.stage);
+    const bool fused_v = kFused && a.grad_v;
+    if (fused_v) LdsAcc{nullptr, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots}.init();
+    const TileIo io{a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, nullptr, Touch{}, a.stage};
     for (;;) {
-        unsigned t = 0;
-        if (lane == 0) t = atomicAdd(a.counter, 1u);
-        t = (unsigned)__builtin_amdgcn_readfirstlane((int)t);
+        __syncthreads();  // the previous item is done with LDS and item_sh
+        if (threadIdx.x == 0) item_sh = atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const unsigned t = item_sh;
         if (t >= (unsigned)a.n_items) break;
-        const int mi = __builtin_amdgcn_readfirstlane(a.item_mesh[t]);
-        const int64_t first = a.item_first[t];
-        const int64_t count = a.q_off[mi + 1] - a.q_off[mi];
-        const int64_t last = min(first + (int64_t)a.tile, count);
-        const DevMesh m = meshes[mi];
+        const int mi = __builtin_amdgcn_readfirstlane(gload(a.item_mesh + t));
+        const int64_t first = gload(a.item_first + t);
+        const int64_t base = gload(a.q_off + mi);
+        const int64_t last = min(first + (int64_t)a.tile, gload(a.q_off + mi + 1) - base);
+        const DevMesh& m = meshes[mi];  // fields loaded as needed (scalar loads), not all kept live
         const int32_t* perm = a.perm[mi];
-        float* gv = kFused ? a.grad_v[mi] : nullptr;
-        const LdsAcc acc{gv, wkeys, wval, kWaveSlots};
-        const int64_t base = a.q_off[mi];
-        // wave-uniform trip count: every lane takes part in each run_query
-        for (int64_t j0 = first; j0 < last; j0 += 64) {
-            const int64_t j = j0 + lane;
+        float* gv = fused_v ? a.grad_v[mi] : nullptr;
+        const LdsAcc acc{gv, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
+        // workgroup-uniform trip count: every thread takes part in each tile
+        for (int64_t j0 = first; j0 < last; j0 += blockDim.x) {
+            if (j0 != first) __syncthreads();  // the previous tile is done with the regroup's area
+            for (int k = threadIdx.x; k < nw * 256; k += blockDim.x) smem[k] = 0;
+            __syncthreads();
+            const int64_t j = j0 + threadIdx.x;
             const bool valid = j < last;
             const int64_t i = valid ? base + (perm ? (int64_t)gload(perm + j) : j) : 0;
-            run_query<kFused, false>(m, valid, i, i, a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, acc,
-                                     nullptr);
-            if (kFused && gv) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                for (int k = lane; k < kWaveSlots; k += 64) {
-                    const int key = wkeys[k];
-                    if (key >= 0) {
-                        DirectAcc{gv}.add(key, wval[3 * k], wval[3 * k + 1], wval[3 * k + 2]);
-                        wkeys[k] = -1;
-                        wval[3 * k] = 0.f;
-                        wval[3 * k + 1] = 0.f;
-                        wval[3 * k + 2] = 0.f;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
+            search_tile<kFused, false>(m, smem, io, acc, valid, i, i);
         }
+        if (fused_v && gv) {
+            __syncthreads();
+            acc.flush_clear();
+        }
+    }
+}
+
+// The batched form without the queue: one workgroup per work item (a tile
+// of blockDim queries of one mesh, items in largest-mesh-first order), the
+// hardware's dispatcher handing out the workgroups as slots free up.  The
+// same per-tile search as the plain kernel, with the mesh looked up per
+// workgroup.
+template <bool kFused>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(7, 8))) batch_tile_kernel(
+    const DevMesh* __restrict__ meshes, const BatchArgs a)
+{
+    extern __shared__ __align__(16) int smem[];
+    const int nw = (int)(blockDim.x >> 6);
+    const int t = (int)blockIdx.x;
+    const int mi = __builtin_amdgcn_readfirstlane(gload(a.item_mesh + t));
+    const int64_t first = gload(a.item_first + t);
+    const int64_t base = gload(a.q_off + mi);
+    const int64_t last = min(first + (int64_t)a.tile, gload(a.q_off + mi + 1) - base);
+    const DevMesh& m = meshes[mi];
+    const int32_t* perm = a.perm[mi];
+    float* gv = kFused && a.grad_v ? a.grad_v[mi] : nullptr;
+    int* acc_smem = smem + search_lds_ints((int)blockDim.x, a.stage);
+    const LdsAcc acc{gv, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
+    for (int k = threadIdx.x; k < nw * 256; k += blockDim.x) smem[k] = 0;
+    if (kFused && gv) acc.init();
+    __syncthreads();
+    const TileIo io{a.q, a.dist, a.tri, a.closest, a.grad_dist, a.grad_q, nullptr, Touch{}, a.stage};
+    const int64_t j = first + threadIdx.x;
+    const bool valid = j < last;
+    const int64_t i = valid ? base + (perm ? (int64_t)gload(perm + j) : j) : 0;
+    search_tile<kFused, false>(m, smem, io, acc, valid, i, i);
+    if (kFused && gv) {
+        __syncthreads();
+        acc.flush();
     }
 }
 
@@ -1687,11 +1682,28 @@ hipError_t launch_reorder(const DevMesh& m, const float* q, int64_t n, int bits,
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int block, bool fused,
+hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int block, bool fused, int stage,
                         hipStream_t st)
 {
-    if (fused) batch_kernel<true><<<grid, block, (size_t)(block / 64) * kWaveSlots * 16, st>>>(meshes, a);
-    else batch_kernel<false><<<grid, block, 0, st>>>(meshes, a);
+    BatchArgs args = a;
+    // grid <= 0: one workgroup per work item (a.tile == block), no queue
+    const bool direct = grid <= 0;
+    if (direct && a.tile != block) return hipErrorInvalidValue;
+    // as launch_forward: the staging area within 48 KB, the fused table
+    // within 64 KB of LDS together with the search's area
+    args.stage = stage > 0 ? std::min(kStageEntries, 49152 / (16 * (block / 64))) : 0;
+    const size_t rg_bytes = 4 * (size_t)search_lds_ints(block, args.stage);
+    if (fused) {
+        int slots = acc_slots_for(block);
+        while (slots > 64 && rg_bytes + acc_lds_bytes(slots) > 65536) slots >>= 1;
+        args.acc_slots = slots;
+        const size_t lds = rg_bytes + (a.grad_v ? acc_lds_bytes(slots) : 0);
+        if (direct) batch_tile_kernel<true><<<(unsigned)a.n_items, block, lds, st>>>(meshes, args);
+        else batch_kernel<true><<<grid, block, lds, st>>>(meshes, args);
+    } else {
+        if (direct) batch_tile_kernel<false><<<(unsigned)a.n_items, block, rg_bytes, st>>>(meshes, args);
+        else batch_kernel<false><<<grid, block, rg_bytes, st>>>(meshes, args);
+    }
     return hipGetLastError();
 }
 

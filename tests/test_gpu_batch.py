@@ -108,6 +108,49 @@ def test_batched_fused_equals_plain(dev, c4_small):
             assert err <= 1e-5, (rep, i, err)
 
 
+@pytest.mark.parametrize("tile,grid,block,stage", [(256, 0, 256, 0), (512, 0, 512, 1), (2048, 512, 256, 0),
+                                                   (1024, 1024, 512, 1)])
+def test_batched_launch_modes_equal_plain(dev, c4_small, tile, grid, block, stage):
+    """Both launch modes (one workgroup per item, or a persistent grid taking
+    items from the queue), at two workgroup sizes, with and without LDS
+    staging: forward and fused outputs equal one plain call per mesh bit for
+    bit (dL/dV up to the order of float32 additions)."""
+    cfg, meshes = c4_small
+    Q, off = concat_points(cfg)
+    n = len(Q)
+    q = torch.from_numpy(Q).cuda()
+    g = torch.from_numpy(np.random.default_rng(33).normal(size=n).astype(np.float32)).cuda()
+    dist = torch.empty(n, device="cuda")
+    tri = torch.empty(n, dtype=torch.int32, device="cuda")
+    cl = torch.empty((n, 3), device="cuda")
+    gq = torch.empty((n, 3), device="cuda")
+    gvs = [torch.zeros((len(m.V), 3), device="cuda") for m in meshes]
+    b = dev.Batch(meshes, [len(c["Q"]) for c in cfg], autotune=False)
+    b.set_config(tile, grid, block, stage)
+    b.bind(q, dist, tri, cl)
+    assert b.config() == {"tile": tile, "grid": grid, "block": block, "stage": stage}
+    bf = dev.Batch(meshes, [len(c["Q"]) for c in cfg], autotune=False)
+    bf.set_config(tile, grid, block, stage)
+    bf.bind(q, torch.empty_like(dist), torch.empty_like(tri), torch.empty_like(cl), grad_dist=g, grad_points=gq,
+            grad_vertices=gvs)
+    for rep in range(2):
+        for t in gvs:
+            t.zero_()
+        b.launch()
+        bf.launch()
+        torch.cuda.synchronize()
+        for i, m in enumerate(meshes):
+            s = slice(off[i], off[i + 1])
+            d, t, c = dev.query(m, q[s].contiguous())
+            gv_ref = torch.zeros_like(gvs[i])
+            _, _, _, gq_ref = dev.query_fused(m, q[s].contiguous(), g[s].contiguous(), grad_vertices=gv_ref)
+            torch.cuda.synchronize()
+            assert torch.equal(dist[s], d) and torch.equal(tri[s], t) and torch.equal(cl[s], c), (rep, i)
+            assert torch.equal(gq[s], gq_ref), (rep, i)
+            err = torch.linalg.norm(gvs[i] - gv_ref) / max(torch.linalg.norm(gv_ref).item(), 1e-30)
+            assert err <= 1e-5, (rep, i, err)
+
+
 def test_batched_fused_against_oracle_gradient(dev, c4_small):
     """The batched fused form's dL/dq and every mesh's dL/dV against the
     FP64 envelope-theorem gradient of the oracle (at the GPU's triangles;
@@ -167,3 +210,35 @@ def test_batched_plan_prefix_full_meshes(dev):
         idx = np.arange(off[i], off[i] + k)
         check_forward(cfg[i]["V"], cfg[i]["F"], Q[idx], to_np(dist)[idx], to_np(tri)[idx], to_np(cl)[idx],
                       cfg[i]["D"], label=cfg[i]["name"])
+
+
+def test_batched_full_plan(dev):
+    """The whole 64-mesh plan at its stated size (7.35M triangles, 16.9M
+    points; built with the device preprocessing): the batched forward, in
+    the configuration the autotuner picks, equals one plain call per mesh
+    bit for bit, and 200 points of every mesh match the oracle."""
+    import time
+    t0 = time.time()
+    cfg = gen.config_c4(gen.c4_plan())
+    meshes = [dev.Mesh(c["V"], c["F"]) for c in cfg]
+    print(f"64 meshes built in {time.time() - t0:.1f}s")
+    Q, off = concat_points(cfg)
+    n = len(Q)
+    q = torch.from_numpy(Q).cuda()
+    dist = torch.empty(n, device="cuda")
+    tri = torch.empty(n, dtype=torch.int32, device="cuda")
+    cl = torch.empty((n, 3), device="cuda")
+    b = dev.Batch(meshes, [len(c["Q"]) for c in cfg], autotune=True)
+    b.bind(q, dist, tri, cl)
+    b.launch()
+    torch.cuda.synchronize()
+    print(f"launch configuration {b.config()}")
+    dn, tn, cn = to_np(dist), to_np(tri), to_np(cl)
+    for i, m in enumerate(meshes):
+        s = slice(off[i], off[i + 1])
+        d, t, c = dev.query(m, q[s].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(dist[s], d) and torch.equal(tri[s], t) and torch.equal(cl[s], c), i
+        idx = np.arange(off[i], off[i] + min(200, off[i + 1] - off[i]))
+        check_forward(cfg[i]["V"], cfg[i]["F"], Q[idx], dn[idx], tn[idx], cn[idx], cfg[i]["D"], label=cfg[i]["name"])
+
