@@ -90,7 +90,7 @@ typedef struct {
     int32_t octree_max_list;   /* octree: split a box while its list is longer (64) */
     int32_t octree_max_depth;  /* octree: at most this many levels below the root (12, <= 16) */
     int32_t gpu_lists;         /* 1: the list stage's sphere-union tests run on the device
-                                  (same lists; sites with more than 64 balls stay on the
+                                  (same lists; sites with more than 256 balls stay on the
                                   host); 0: all on the host (default 1; needs device >= 0) */
     int32_t gpu_voronoi;       /* 1: the Voronoi stage's corner checks (is a site closer than
                                   the cell's own to this corner?) run on the device, in rounds

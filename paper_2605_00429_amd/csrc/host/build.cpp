@@ -130,6 +130,13 @@ constexpr int kKnn = 24;
 // Sites one corner check of the first (density) pass may examine; ordinary
 // checks examine a few dozen.
 constexpr int64_t kPass1Budget = 4096;
+// A budgeted cell that has gained more faces than this stops refining and
+// counts as unresolved.  Before the auxiliary sites exist, the cell of a
+// vertex on a rotational axis (the centre of a cylinder's cap) is cut by
+// nearly every vertex of the wall, and clipping tens of thousands of faces
+// one plane at a time is quadratic; such cells are built again, exactly,
+// once the auxiliary sites cut them off.
+constexpr int32_t kPass1MaxFaces = 4096;
 // Float32 input positions break exact co-sphericity at the 1e-7 level; a
 // violation smaller than this is rounding noise of a degenerate corner.
 constexpr double kCornerSlack = 1e-6;
@@ -176,8 +183,8 @@ void collect_pending(CellState& c, std::vector<d3>& corners)
 // is clipped by, a corner with no closer site is final.  The cell stays in
 // progress, with its new corners pending, when some site was found.
 template <class Res>
-void apply_round(CellState& c, const Res& res, const std::vector<d3>& P, d3 ps, std::vector<int32_t>& found,
-                 std::vector<d3>& corners)
+void apply_round(CellState& c, const Res& res, const std::vector<d3>& P, d3 ps, bool budgeted,
+                 std::vector<int32_t>& found, std::vector<d3>& corners)
 {
     found.clear();
     for (size_t k = 0; k < c.pending.size(); ++k) {
@@ -198,6 +205,12 @@ void apply_round(CellState& c, const Res& res, const std::vector<d3>& P, d3 ps, 
         const d3 nv = P[f] - ps;
         c.cell.clip(nv, 0.5 * norm2(nv), f);
         c.tested.insert(std::upper_bound(c.tested.begin(), c.tested.end(), f), f);
+    }
+    if (budgeted && c.cell.n_faces() > kPass1MaxFaces) {
+        c.unresolved = true;
+        c.active = false;
+        c.pending.clear();
+        return;
     }
     collect_pending(c, corners);
 }
@@ -220,8 +233,9 @@ constexpr int64_t kHostTail = 256;
 //      corners; cells with nothing found are final.  Rounds repeat until
 //      no cell is in progress; the last few cells run their remaining
 //      rounds on the host (KdTree::below gives the same answers).
-// With budget >= 0 each check examines at most that many sites; a check
-// that gives up leaves the cell a superset and marks it unresolved.  That
+// With budget >= 0 each check examines at most that many sites, and a cell
+// stops refining past kPass1MaxFaces faces; a check that gives up, or that
+// cap, leaves the cell a superset and marks it unresolved.  That
 // happens at corners that nearly all sites are almost equidistant from
 // (the centre of a sphere tessellation, the axis of a cylinder).  done(i,
 // tid, corners, faces, ok, unresolved) receives sites[i]'s cell inside a
@@ -286,7 +300,7 @@ void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, 
                         for (size_t k = 0; k < c.pending.size(); ++k)
                             w.res[k] = kd.below(ps + c.pending[k], corner_limit(c.pending[k]), c.tested.data(),
                                                 c.tested.data() + c.tested.size(), budget);
-                        apply_round(c, [&](size_t k) { return w.res[k]; }, P, ps, w.found, w.corners);
+                        apply_round(c, [&](size_t k) { return w.res[k]; }, P, ps, budget >= 0, w.found, w.corners);
                     }
                 }, 1);
                 act.clear();
@@ -316,8 +330,8 @@ void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, 
                 CellState& c = st[act[j]];
                 Scratch& w = scr[tid];
                 const int64_t first = c.first;
-                apply_round(c, [&](size_t k) { return res[first + (int64_t)k]; }, P, P[sites[c0 + act[j]]], w.found,
-                            w.corners);
+                apply_round(c, [&](size_t k) { return res[first + (int64_t)k]; }, P, P[sites[c0 + act[j]]],
+                            budget >= 0, w.found, w.corners);
             }, 16);
             std::vector<int64_t> next;
             for (int64_t i : act)
@@ -896,7 +910,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             }
             w.balls.resize(k);
         }
-        if (gpu && !w.balls.empty() && w.balls.size() <= 64) {
+        if (gpu && !w.balls.empty() && w.balls.size() <= (size_t)kDeviceBalls) {
             dev_balls[s] = w.balls;  // tested on the device below
             return;
         }

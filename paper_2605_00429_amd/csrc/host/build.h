@@ -71,7 +71,8 @@ class Bvh;
 
 // The sphere-union tests of the list stage, handed to a device: for each
 // site in `sites`, its balls (4 doubles each: centre, radius) in
-// balls[4 * ball_off[i] .. 4 * ball_off[i + 1]), at most 64 per site.
+// balls[4 * ball_off[i] .. 4 * ball_off[i + 1]), at most kDeviceBalls per site.
+constexpr int kDeviceBalls = 256;
 struct GpuListJob {
     const std::vector<d3>* tri = nullptr;  // 3 vertices per triangle (FP64)
     const Bvh* bvh = nullptr;
@@ -104,7 +105,7 @@ struct CornerChecks {
 using CheckFn = std::function<void(const CornerChecks&, std::vector<int32_t>& out)>;
 
 // Throws p2m::Error on invalid input.  With `gpu`, the list stage's
-// sphere-union tests run through it (sites with more than 64 balls stay on
+// sphere-union tests run through it (sites with more than kDeviceBalls balls stay on
 // the host); with `gpu_checks`, the Voronoi stage's corner checks do.  The
 // structure is the same either way.
 void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& opts, HostStructure& out,

@@ -3,11 +3,11 @@
 // single sphere of Eq. (8)), by a traversal of the mesh BVH.
 //
 // The host computes the Voronoi cells and the balls; this file takes over
-// the sphere-union tests.  It reproduces the host's traversal exactly: the
-// same BVH, the same 64-ball masks, the same box and triangle-box
+// the sphere-union tests.  It reproduces the host's decisions exactly: the
+// same BVH, the same per-node ball masks, the same box and triangle-box
 // prefilters and the same FP64 point-triangle distance, evaluated in the
 // same operation order with no contraction into fused multiply-adds, so
-// both paths give identical lists (in identical order).
+// both paths give identical lists.
 #pragma clang fp contract(off)
 
 #include <hip/hip_runtime.h>
@@ -107,69 +107,98 @@ __device__ double tri_dist2(G3 q, G3 a, G3 b, G3 c)
     return gdot(r, r);
 }
 
+// Balls per lane: a wavefront holds up to 64 * kLaneBalls balls of one site.
+constexpr int kLaneBalls = 4;
 constexpr int kStack = 64;
+constexpr int kWaves = 4;  // wavefronts (sites) per workgroup
 
-// One site per thread.  Pass 1 (kFill = false) counts, pass 2 writes the
+// One wavefront per site, its balls spread over the lanes (ball k on lane
+// k % 64).  The wavefront walks the BVH depth first as one: at each node
+// every lane tests its live balls against the box (live = passed every
+// ancestor's box, as in the host's per-node masks), and the node is skipped
+// when no lane has one left; at a leaf, a triangle is in the list when any
+// lane's live ball passes the triangle-box prefilter and the exact distance
+// test.  The node and triangle loads are the same for the whole wavefront.
+// The set of triangles is the host's (its order, which the layout stage
+// re-sorts, is not).  Pass 1 (kFill = false) counts, pass 2 writes the
 // triangle ids from off[site].  A traversal that would overflow its stack
 // (never for a BVH of at most 2^29 triangles) reports count -1, and the
 // host builds that list itself.
+static_assert(64 * kLaneBalls >= kDeviceBalls, "a wavefront must hold every ball the host sends");
+
 template <bool kFill>
-__global__ void __launch_bounds__(256) list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order,
-                                                    const double* __restrict__ T, const int64_t* __restrict__ ball_off,
-                                                    const double* __restrict__ balls, int64_t n_sites,
-                                                    int64_t* __restrict__ counts, const int64_t* __restrict__ off,
-                                                    int32_t* __restrict__ ids)
+__global__ void __launch_bounds__(64 * kWaves)
+list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, const double* __restrict__ T,
+            const int64_t* __restrict__ ball_off, const double* __restrict__ balls, int64_t n_sites,
+            int64_t* __restrict__ counts, const int64_t* __restrict__ off, int32_t* __restrict__ ids)
 {
-    const int64_t si = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (si >= n_sites) return;
+    __shared__ int32_t s_node[kWaves][kStack];
+    __shared__ uint8_t s_mask[kWaves][kStack][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t si = (int64_t)blockIdx.x * kWaves + wv;
+    if (si >= n_sites) return;  // the whole wavefront
+    if (kFill && counts[si] < 0) return;
     const int64_t b0 = ball_off[si];
     const int nb = (int)(ball_off[si + 1] - b0);
-    if (kFill && counts[si] < 0) return;
-    const double* B = balls + 4 * b0;
+    double bx[kLaneBalls], by[kLaneBalls], bz[kLaneBalls], r2[kLaneBalls];
+    unsigned live = 0;
+#pragma unroll
+    for (int j = 0; j < kLaneBalls; ++j) {
+        const int k = lane + 64 * j;
+        bx[j] = by[j] = bz[j] = r2[j] = 0.0;
+        if (k < nb) {
+            const double* B = balls + 4 * (b0 + k);
+            bx[j] = B[0];
+            by[j] = B[1];
+            bz[j] = B[2];
+            r2[j] = B[3] * B[3];
+            live |= 1u << j;
+        }
+    }
     int64_t cnt = 0;
     int64_t w = kFill ? off[si] : 0;
-    struct Item {
-        int32_t node;
-        uint64_t mask;
-    } stack[kStack];
     int sp = 0;
-    if (nb > 0) stack[sp++] = {0, nb == 64 ? ~0ULL : ((1ULL << nb) - 1)};
+    // every lane writes the same node id, and reads back what it wrote
+    s_node[wv][sp] = 0;
+    s_mask[wv][sp][lane] = (uint8_t)live;
+    ++sp;
     bool overflow = false;
     while (sp > 0) {
-        const Item it = stack[--sp];
-        const GNode n = nodes[it.node];
-        uint64_t m = 0;
-        for (uint64_t r = it.mask; r; r &= r - 1) {
-            const int k = __builtin_ctzll(r);
-            const double cx = B[4 * k], cy = B[4 * k + 1], cz = B[4 * k + 2], rr = B[4 * k + 3];
-            const double dx = gmax3(n.lo[0] - cx, 0.0, cx - n.hi[0]);
-            const double dy = gmax3(n.lo[1] - cy, 0.0, cy - n.hi[1]);
-            const double dz = gmax3(n.lo[2] - cz, 0.0, cz - n.hi[2]);
-            if (dx * dx + dy * dy + dz * dz <= rr * rr) m |= 1ULL << k;
+        --sp;
+        const int32_t node = __builtin_amdgcn_readfirstlane(s_node[wv][sp]);
+        const unsigned lm = s_mask[wv][sp][lane];
+        const GNode n = nodes[node];
+        unsigned m = 0;
+#pragma unroll
+        for (int j = 0; j < kLaneBalls; ++j) {
+            if (!((lm >> j) & 1u)) continue;
+            const double dx = gmax3(n.lo[0] - bx[j], 0.0, bx[j] - n.hi[0]);
+            const double dy = gmax3(n.lo[1] - by[j], 0.0, by[j] - n.hi[1]);
+            const double dz = gmax3(n.lo[2] - bz[j], 0.0, bz[j] - n.hi[2]);
+            if (dx * dx + dy * dy + dz * dz <= r2[j]) m |= 1u << j;
         }
-        if (!m) continue;
+        if (__ballot(m != 0) == 0) continue;
         if (n.b < 0) {
             for (int32_t i = n.a; i < n.a - n.b; ++i) {
                 const int32_t t = order[i];
-                const G3 a{T[9 * (int64_t)t], T[9 * (int64_t)t + 1], T[9 * (int64_t)t + 2]};
-                const G3 b{T[9 * (int64_t)t + 3], T[9 * (int64_t)t + 4], T[9 * (int64_t)t + 5]};
-                const G3 c{T[9 * (int64_t)t + 6], T[9 * (int64_t)t + 7], T[9 * (int64_t)t + 8]};
+                const double* tp = T + 9 * (int64_t)t;
+                const G3 a{tp[0], tp[1], tp[2]}, b{tp[3], tp[4], tp[5]}, c{tp[6], tp[7], tp[8]};
                 const G3 lo{fmin(a.x, fmin(b.x, c.x)), fmin(a.y, fmin(b.y, c.y)), fmin(a.z, fmin(b.z, c.z))};
                 const G3 hi{fmax(a.x, fmax(b.x, c.x)), fmax(a.y, fmax(b.y, c.y)), fmax(a.z, fmax(b.z, c.z))};
-                for (uint64_t r = m; r; r &= r - 1) {
-                    const int k = __builtin_ctzll(r);
-                    const G3 q{B[4 * k], B[4 * k + 1], B[4 * k + 2]};
-                    const double r2 = B[4 * k + 3] * B[4 * k + 3];
-                    const double dx = gmax3(lo.x - q.x, 0.0, q.x - hi.x);
-                    const double dy = gmax3(lo.y - q.y, 0.0, q.y - hi.y);
-                    const double dz = gmax3(lo.z - q.z, 0.0, q.z - hi.z);
-                    if (dx * dx + dy * dy + dz * dz > r2) continue;
-                    if (tri_dist2(q, a, b, c) <= r2) {
-                        if (kFill) ids[w] = t;
-                        ++w;
-                        ++cnt;
-                        break;
-                    }
+                bool hit = false;
+#pragma unroll
+                for (int j = 0; j < kLaneBalls; ++j) {
+                    if (hit || !((m >> j) & 1u)) continue;
+                    const double dx = gmax3(lo.x - bx[j], 0.0, bx[j] - hi.x);
+                    const double dy = gmax3(lo.y - by[j], 0.0, by[j] - hi.y);
+                    const double dz = gmax3(lo.z - bz[j], 0.0, bz[j] - hi.z);
+                    if (dx * dx + dy * dy + dz * dz > r2[j]) continue;
+                    hit = tri_dist2(G3{bx[j], by[j], bz[j]}, a, b, c) <= r2[j];
+                }
+                if (__ballot(hit) != 0) {
+                    if (kFill && lane == 0) ids[w] = t;
+                    ++w;
+                    ++cnt;
                 }
             }
             continue;
@@ -178,10 +207,14 @@ __global__ void __launch_bounds__(256) list_kernel(const GNode* __restrict__ nod
             overflow = true;
             break;
         }
-        stack[sp++] = {n.b, m};
-        stack[sp++] = {it.node + 1, m};
+        s_node[wv][sp] = n.b;
+        s_mask[wv][sp][lane] = (uint8_t)m;
+        ++sp;
+        s_node[wv][sp] = node + 1;
+        s_mask[wv][sp][lane] = (uint8_t)m;
+        ++sp;
     }
-    if (!kFill) counts[si] = overflow ? -1 : cnt;
+    if (!kFill && lane == 0) counts[si] = overflow ? -1 : cnt;
 }
 
 struct DevBuf {
@@ -239,8 +272,8 @@ void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vect
     upload(d_boff, job.ball_off.data(), job.ball_off.size());
     upload(d_balls, job.balls.data(), job.balls.size());
     check(hipMalloc(&d_counts.p, ns * sizeof(int64_t)), "hipMalloc (list build)");
-    const int block = 256;
-    const int grid = (int)((ns + block - 1) / block);
+    const int block = 64 * kWaves;
+    const int grid = (int)((ns + kWaves - 1) / kWaves);
     list_kernel<false><<<grid, block>>>(d_nodes.get<GNode>(), d_order.get<int32_t>(), d_T.get<double>(),
                                         d_boff.get<int64_t>(), d_balls.get<double>(), ns, d_counts.get<int64_t>(),
                                         nullptr, nullptr);

@@ -220,7 +220,10 @@ def test_batched_full_plan(dev):
     import time
     t0 = time.time()
     cfg = gen.config_c4(gen.c4_plan())
-    meshes = [dev.Mesh(c["V"], c["F"]) for c in cfg]
+    meshes = []
+    for k, c in enumerate(cfg):
+        meshes.append(dev.Mesh(c["V"], c["F"]))
+        print(f"mesh {k + 1}/64 ({c['name']}, {len(c['F'])} triangles) built at {time.time() - t0:.1f}s", flush=True)
     print(f"64 meshes built in {time.time() - t0:.1f}s")
     Q, off = concat_points(cfg)
     n = len(Q)
