@@ -157,6 +157,8 @@ def bench_batched(args, plain_c2_mqps, stream):
     off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     n_tris = int(sum(len(c["F"]) for c in cfg))
     n_verts = [len(c["V"]) for c in cfg]
+    n_tri_each = [len(c["F"]) for c in cfg]
+    kinds = [c["name"].split()[-1] for c in cfg]
     log(f"batched workload: {len(cfg)} meshes, {n_tris} triangles, {n} points; build {build_s:.1f}s")
     dev = torch.device("cuda", 0)
     q = torch.from_numpy(np.concatenate([c["Q"] for c in cfg], 0)).to(dev)
@@ -177,9 +179,11 @@ def bench_batched(args, plain_c2_mqps, stream):
     # compulsory bytes: per-mesh instrumented forwards (untimed), each
     # mesh's distinct structure items plus every point's input and output
     comp = 0.0
+    ctrs = []
     for i, m in enumerate(meshes):
+        ctrs.append(None)
         if counts[i]:
-            _, _, _, _, items = p2m.query_touched(m, qs[i])
+            _, _, _, ctrs[i], items = p2m.query_touched(m, qs[i])
             comp += compulsory_bytes(items, counts[i])
     torch.cuda.synchronize()
 
@@ -207,6 +211,29 @@ def bench_batched(args, plain_c2_mqps, stream):
         b_fus.launch(stream=stream)
 
     steps, warm = max(3, args.steps // 2), max(1, args.warmup)
+    # where the time goes: each mesh's plain forward timed alone, summed by
+    # mesh kind with the instrumented per-query counts
+    by_kind = {}
+    for i, m in enumerate(meshes):
+        if not counts[i]:
+            continue
+        ms_i = timed(lambda: p2m.lib().p2m_query(m.handle, p2m._ptr(qs[i]), counts[i], p2m._ptr(outs[i][0]),
+                                                 p2m._ptr(outs[i][1]), p2m._ptr(outs[i][2]), p2m._stream(stream)),
+                     3, 1, stream)
+        k = by_kind.setdefault(kinds[i], {"meshes": 0, "points": 0, "triangles": 0, "plain_ms": 0.0,
+                                          "list_len": 0, "list_read": 0, "exact_tests": 0})
+        k["meshes"] += 1
+        k["points"] += counts[i]
+        k["triangles"] += n_tri_each[i]
+        k["plain_ms"] += ms_i
+        for c in ("list_len", "list_read", "exact_tests"):
+            k[c] += ctrs[i][c]
+    for k in by_kind.values():
+        k["plain_ms"] = round(k["plain_ms"], 3)
+        k["mqps"] = round(k["points"] / (k["plain_ms"] * 1e-3) / 1e6, 1)
+        for c in ("list_len", "list_read", "exact_tests"):
+            k[c] = round(k[c] / max(k["points"], 1), 1)
+        k["queried"] = k.pop("list_len")
     ms_b = timed(lambda: b_fwd.launch(stream=stream), steps, warm, stream)
     ms_p = timed(plain_fwd, steps, warm, stream)
     ms_bf = timed(batched_fused, steps, warm, stream)
@@ -214,8 +241,8 @@ def bench_batched(args, plain_c2_mqps, stream):
     mq = lambda ms: round(n / (ms * 1e-3) / 1e6, 2)
     gbs = lambda per, ms: round(per / (ms * 1e-3) / 1e9, 1)
     res = {
-        "workload": f"the first {len(meshes)} of a 64-mesh plan (uv sphere, capped cylinder, capped cone, torus, "
-                    "displaced icosphere): "
+        "workload": (f"the 64-mesh plan" if len(meshes) == 64 else f"the first {len(meshes)} of a 64-mesh plan") +
+                    " (uv sphere, capped cylinder, capped cone, torus, displaced icosphere): "
                     f"{n_tris} triangles, log-uniform 1e3-5e5 per mesh; {n} points, log-uniform 1e4-2e6 per "
                     "mesh, half uniform in box x1.2, half near-surface sigma 0.5% diag",
         "n_points": n, "n_triangles": n_tris, "build_s": round(build_s, 1),
@@ -231,6 +258,7 @@ def bench_batched(args, plain_c2_mqps, stream):
         "fwd_compulsory_frac": round(gbs(comp, ms_b) / HBM_PEAK_GBS, 4),
         "fwd_bwd_compulsory_GBps": gbs(comp + GRAD_IO_BYTES * n + 24 * int(voff[-1]), ms_bf),
         "launch_config": b_fwd.config(),
+        "by_kind": by_kind,
     }
     log(f"batched forward {ms_b:.3f} ms ({res['fwd_mqps']:.1f} Mq/s) vs {len(meshes)} plain calls "
         f"{ms_p:.3f} ms; fused batched {ms_bf:.3f} ms vs plain {ms_pf:.3f} ms")
@@ -468,9 +496,9 @@ def main():
     ap.add_argument("--no-point-set", action="store_true",
                     help="skip the point-set distance measurement (profiling runs: it launches the search "
                          "kernel with fewer outputs)")
-    ap.add_argument("--batched-meshes", type=int, default=11,
-                    help="meshes of the batched workload: the first k of its 64-mesh plan (all 64 take "
-                         "about 9 minutes of host preprocessing on 16 threads)")
+    ap.add_argument("--batched-meshes", type=int, default=64,
+                    help="meshes of the batched workload: the first k of its 64-mesh plan (all 64: about "
+                         "2 minutes of preprocessing)")
     ap.add_argument("--octree", action="store_true",
                     help="add the octree decomposition (leaf boxes instead of Voronoi cells) on the same workload")
     ap.add_argument("--no-ablation", action="store_true",

@@ -797,24 +797,56 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             // drop auxiliary sites whose cells reach the domain box (an
             // unbounded cell would get a list of the whole mesh)
             std::vector<d3> aux = acc;
+            // Only cells next to a dropped site change when it goes, so each
+            // iteration after the first rebuilds just those.
+            std::vector<char> need(aux.size(), 1);
+            std::vector<std::vector<int32_t>> anb(aux.size());  // aux neighbours (aux indices)
             for (int iter = 0; iter < 6 && !aux.empty(); ++iter) {
                 std::vector<d3> PP = P;
                 PP.insert(PP.end(), aux.begin(), aux.end());
                 KdTree kd2;
                 kd2.build(PP);
                 std::vector<char> drop(aux.size(), 0);
-                std::vector<int32_t> asites(aux.size());
-                std::iota(asites.begin(), asites.end(), nVS);
+                std::vector<int32_t> asites;
+                for (size_t i = 0; i < aux.size(); ++i)
+                    if (need[i]) asites.push_back(nVS + (int32_t)i);
                 compute_cells(asites, PP, kd2, blo, bhi, -1, nth, checks, gpu_checks != nullptr,
-                              [&](int64_t i, int, const std::vector<d3>&, const std::vector<int32_t>& faces, bool ok,
+                              [&](int64_t j, int, const std::vector<d3>&, const std::vector<int32_t>& faces, bool ok,
                                   bool) {
+                    const int32_t i = asites[j] - nVS;
                     if (faces.empty() || faces.front() < 0 || !ok) drop[i] = 1;
+                    anb[i].clear();
+                    for (int32_t f : faces)
+                        if (f >= nVS) anb[i].push_back(f - nVS);
                 });
+                std::vector<int32_t> newid(aux.size(), -1);
                 std::vector<d3> keep;
                 for (size_t i = 0; i < aux.size(); ++i)
-                    if (!drop[i]) keep.push_back(aux[i]);
+                    if (!drop[i]) {
+                        newid[i] = (int32_t)keep.size();
+                        keep.push_back(aux[i]);
+                    }
                 const bool stable = keep.size() == aux.size();
+                std::vector<char> need2(keep.size(), 0);
+                for (size_t i = 0; i < aux.size(); ++i) {
+                    if (!drop[i]) continue;
+                    for (int32_t f : anb[i])
+                        if (newid[f] >= 0) need2[newid[f]] = 1;
+                }
+                for (size_t i = 0; i < aux.size(); ++i) {
+                    if (drop[i]) continue;
+                    for (int32_t f : anb[i])
+                        if (drop[f]) need2[newid[i]] = 1;
+                }
+                std::vector<std::vector<int32_t>> anb2(keep.size());
+                for (size_t i = 0; i < aux.size(); ++i) {
+                    if (drop[i]) continue;
+                    for (int32_t f : anb[i])
+                        if (newid[f] >= 0) anb2[newid[i]].push_back(newid[f]);
+                }
                 aux.swap(keep);
+                need.swap(need2);
+                anb.swap(anb2);
                 if (stable) break;
             }
             // Vertex cells reused from pass 1 unless an auxiliary site is
