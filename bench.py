@@ -627,12 +627,18 @@ def main():
     }
 
     kh = kernel_source_hash()
+    # which search the library ran (p2m_query_config.group; 2 = automatic)
+    grp = mesh.query_config()["group"]
+    grouped = grp == 1 or (grp == 2 and n >= 16 * st["n_sites"])
+    search_path = ("search phase of p2m_query_ordered: locate_kernel, sort by site, grouped_kernel "
+                   "(list chunks shared through LDS)" if grouped else
+                   "search phase of p2m_query_ordered: fwd_kernel (walk, regroup, per-lane list scans)")
     achieved = comp / (search_avg * 1e-3) / 1e9
     traffic = load_traffic(kh, n)
     result["roofline"] = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-        "kernel": "fwd_kernel (search: locate + list scan)", "kernel_ms": round(search_avg, 4),
+        "kernel": search_path, "kernel_ms": round(search_avg, 4),
         "compulsory_bytes_per_launch": int(comp), "compulsory_bytes_per_query": round(comp / n, 1),
         "structure_items_read": {k: v[0] for k, v in items.items()},
         "touched_bytes_per_query": round(bpq, 1),

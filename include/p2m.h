@@ -126,6 +126,13 @@ typedef struct {
                            lists into LDS with coalesced loads before the list scan (up to 256
                            per wavefront); 0 (default, measured faster on MI355X): the scan
                            gathers them from device memory.  Results are identical. */
+    int32_t group;      /* the search of a non-instrumented query: 0 = one pass (walk, regroup by
+                           site within each workgroup, per-lane list scans); 1 = three passes
+                           (locate every point, sort the points by located site, then each run of
+                           lanes sharing a site scans its list once, loaded 64 entries at a time
+                           through LDS); 2 (default) = the three passes for a forward (not
+                           fused) whose points average at least 16 per site.  Results are
+                           identical. */
 } p2m_query_config;
 
 void p2m_default_opts(p2m_build_opts* opts);

@@ -114,15 +114,18 @@ class Mesh:
         c = _lib.p2m_query_config()
         check(lib().p2m_get_query_config(self.handle, ctypes.byref(c)))
         return {"block_size": c.block_size, "reorder": c.reorder, "xcd_groups": c.xcd_groups,
-                "sort_bits": c.sort_bits, "stage": c.stage}
+                "sort_bits": c.sort_bits, "stage": c.stage, "group": c.group}
 
-    def set_query_config(self, block_size=None, reorder=None, xcd_groups=None, sort_bits=None, stage=None):
+    def set_query_config(self, block_size=None, reorder=None, xcd_groups=None, sort_bits=None, stage=None,
+                         group=None):
+        """Launch configuration of this handle's queries (see p2m_query_config)."""
         cur = self.query_config()
         c = _lib.p2m_query_config(block_size if block_size is not None else cur["block_size"],
                                   int(reorder) if reorder is not None else cur["reorder"],
                                   xcd_groups if xcd_groups is not None else cur["xcd_groups"],
                                   sort_bits if sort_bits is not None else cur["sort_bits"],
-                                  int(stage) if stage is not None else cur["stage"])
+                                  int(stage) if stage is not None else cur["stage"],
+                                  int(group) if group is not None else cur["group"])
         check(lib().p2m_set_query_config(self.handle, ctypes.byref(c)))
 
     def host_sites(self):

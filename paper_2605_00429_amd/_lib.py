@@ -65,7 +65,7 @@ class p2m_stats(ctypes.Structure):
 
 class p2m_query_config(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("reorder", ctypes.c_int32), ("xcd_groups", ctypes.c_int32),
-                ("sort_bits", ctypes.c_int32), ("stage", ctypes.c_int32)]
+                ("sort_bits", ctypes.c_int32), ("stage", ctypes.c_int32), ("group", ctypes.c_int32)]
 
 
 _VP = ctypes.c_void_p

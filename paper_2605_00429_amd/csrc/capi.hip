@@ -55,6 +55,8 @@ struct StreamScratch {
     hipStream_t stream = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    void* gws = nullptr;  // the grouped search's locate keys and site sort
+    size_t gws_bytes = 0;
     void* rws = nullptr;
     size_t rws_bytes = 0;
     double* pair = nullptr;  // mesh distances: the two one-sided reductions (10 doubles)
@@ -66,7 +68,7 @@ struct p2m_handle_ {
     p2m::DevMesh dm{};
     std::vector<void*> allocs;
     int64_t device_bytes = 0;
-    p2m_query_config cfg{256, 1, 1, 0, 0};
+    p2m_query_config cfg{256, 1, 1, 0, 0, 2};
     // the caller's referenced vertices (index order), for mesh distances
     const float* ref_v = nullptr;
     int64_t n_ref = 0;
@@ -80,6 +82,7 @@ struct p2m_handle_ {
             for (void* p : allocs) (void)hipFree(p);
             for (StreamScratch& sc : scratch) {
                 if (sc.ws) (void)hipFree(sc.ws);
+                if (sc.gws) (void)hipFree(sc.gws);
                 if (sc.rws) (void)hipFree(sc.rws);
                 if (sc.pair) (void)hipFree(sc.pair);
             }
@@ -195,6 +198,45 @@ struct p2m_handle_ {
     }
 
     // The point-set reduction buffer of `st`, at least `bytes` (caller holds mu).
+    // The grouped search's workspace of `st`, at least `bytes` (caller holds mu).
+    int32_t ensure_gws(size_t bytes, hipStream_t st, void** out)
+    {
+        StreamScratch& sc = scratch_for(st);
+        const int32_t rc = grow(sc.gws, sc.gws_bytes, bytes, st);
+        *out = sc.gws;
+        return rc;
+    }
+
+    // Whether a non-instrumented search of n points runs as the grouped
+    // passes (locate, sort by site, shared list scans): config group = 1,
+    // or automatic (2) for a forward (not fused) whose points average at
+    // least 16 per site, so that most wavefronts fill up with one site's
+    // points.  Measured on 10M points of the 327k-triangle mesh (61 per
+    // site): search 2.50 against 2.77 ms; fused, 3.81 against 3.68 ms.
+    bool grouped(int64_t n, bool fused) const
+    {
+        if (cfg.group == 0) return false;
+        if (cfg.group == 1) return true;
+        return !fused && n >= 16 * (int64_t)H.n_sites;
+    }
+
+    // The search of `a` (sorted or not): the grouped passes or the one-pass
+    // kernel.  The caller holds mu.
+    int32_t search(const p2m::FwdArgs& a, bool fused, hipStream_t st)
+    {
+        if (grouped(a.n, fused)) {
+            void* gw = nullptr;
+            const int32_t rc = ensure_gws(p2m::grouped_workspace_bytes(a.n, dm.n_sites), st, &gw);
+            if (rc != P2M_OK) return rc;
+            const hipError_t e = p2m::launch_grouped(dm, a, gw, fused, st);
+            if (e != hipSuccess) return hip_fail(e, "grouped search launch");
+            return P2M_OK;
+        }
+        const hipError_t e = p2m::launch_forward(dm, a, cfg.block_size, fused, false, st);
+        if (e != hipSuccess) return hip_fail(e, "forward launch");
+        return P2M_OK;
+    }
+
     int32_t ensure_rws(size_t bytes, hipStream_t st, void** out)
     {
         StreamScratch& sc = scratch_for(st);
@@ -318,6 +360,7 @@ int32_t p2m_set_query_config(p2m_handle h, const p2m_query_config* c)
     if (c->sort_bits < 0 || c->sort_bits > 8)
         return fail(P2M_ERR_INVALID_ARG, "sort_bits must be in [0, 8]");
     if (c->stage != 0 && c->stage != 1) return fail(P2M_ERR_INVALID_ARG, "stage must be 0 or 1");
+    if (c->group < 0 || c->group > 2) return fail(P2M_ERR_INVALID_ARG, "group must be 0, 1 or 2");
     h->cfg = *c;
     return P2M_OK;
 }
@@ -358,7 +401,8 @@ static int32_t query_common(p2m_handle h, const float* q, int64_t n, float* dist
         hipError_t e = p2m::launch_reorder(h->dm, q, n, h->cfg.sort_bits, ws, &a.perm, st);
         if (e != hipSuccess) return hip_fail(e, "reorder launch");
     }
-    hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, fused, ctr != nullptr, st);
+    if (!ctr) return h->search(a, fused, st);
+    hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, fused, true, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return P2M_OK;
 }
@@ -541,9 +585,8 @@ int32_t p2m_query_ordered(p2m_handle h, const float* d_points, const int32_t* d_
     a.closest = d_out_closest;
     a.xcds = h->cfg.xcd_groups;
     a.stage = h->cfg.stage;
-    hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, false, false, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "forward launch");
-    return P2M_OK;
+    std::lock_guard<std::recursive_mutex> lk(h->mu);
+    return h->search(a, false, (hipStream_t)stream);
 }
 
 int32_t p2m_query_sorted(p2m_handle h, const float* d_sorted_points, const int32_t* d_order, int64_t n,
@@ -566,9 +609,8 @@ int32_t p2m_query_sorted(p2m_handle h, const float* d_sorted_points, const int32
     a.closest = d_out_closest;
     a.xcds = h->cfg.xcd_groups;
     a.stage = h->cfg.stage;
-    hipError_t e = p2m::launch_forward(h->dm, a, h->cfg.block_size, false, false, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "forward launch");
-    return P2M_OK;
+    std::lock_guard<std::recursive_mutex> lk(h->mu);
+    return h->search(a, false, (hipStream_t)stream);
 }
 
 int32_t p2m_query_counters(p2m_handle h, const float* d_points, int64_t n, float* d_out_dist,

@@ -122,6 +122,13 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
 hipError_t launch_backward(const DevMesh& m, const float* q, int64_t n, const int32_t* order,
                            const int32_t* tri, const float* g, float* grad_q, float* grad_v, int block,
                            hipStream_t st);
+// The search as three passes for point sets with many points per cell:
+// locate in the visiting order (a.perm / a.q_sorted as launch_forward),
+// sort by located site, scan each site's list once per run of lanes sharing
+// it (through LDS).  Same outputs as launch_forward (not instrumented).
+// ws must hold grouped_workspace_bytes(a.n, m.n_sites) bytes.
+size_t grouped_workspace_bytes(int64_t n, int64_t n_sites);
+hipError_t launch_grouped(const DevMesh& m, const FwdArgs& a, void* ws, bool fused, hipStream_t st);
 // Radix sort of queries by the Morton code of their cell in a 2^k grid
 // over the seed-grid box (k from n when bits = 0).  ws must hold
 // reorder_workspace_bytes(n) bytes; writes the order to *perm_out.

@@ -355,6 +355,45 @@ struct QueryCounts {
 // the scan keeps several requests in flight despite its data-dependent exit.
 constexpr int kChunk = 4;
 
+// One entry of a List Search (entry idx, bounding sphere c): false when the
+// sorted exit fires.  Lists are sorted by ell = |s - c| - r, so no later
+// entry can beat d_min once ell - |q - s| >= d_min (triangle inequality).
+// ell is recomputed from (c, r) rather than loaded, which keeps the scan to
+// one 16-byte load per entry.  The two terms are pulled apart by 1e-6
+// relative, more than the float32 rounding of the differences, the sum of
+// squares, the square root and the subtraction together, so the value never
+// exceeds the exact ell of the same float32 values by which the lists were
+// sorted.  An entry past the sphere prune is tested exactly with its record
+// (rec(f1, f2, f3): first vertex and ell, first edge and e1.e2, second
+// edge and id).  Both scans (per lane, and per group of lanes sharing a
+// site) run this one function, so they decide alike.
+template <class Rec>
+__device__ __forceinline__ bool scan_entry(const float3 q, const float4 sp, const float dqs, const float4 c,
+                                           const int idx, float& dmin, Best& b, unsigned long long& exact,
+                                           Rec rec)
+{
+    const float ux = sp.x - c.x, uy = sp.y - c.y, uz = sp.z - c.z;
+    const float ell = sqrtf(ux * ux + uy * uy + uz * uz) * (1.f - 1e-6f) - c.w * (1.f + 1e-6f);
+    if (ell - dqs >= dmin) return false;
+    const float dx = q.x - c.x, dy = q.y - c.y, dz = q.z - c.z;
+    const float lim = dmin + c.w;
+    if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) return true;
+    float4 f1, f2, f3;
+    rec(f1, f2, f3);
+    float v, w;
+    const float d2 = closest_point(q, make_float3(f1.x, f1.y, f1.z), make_float3(f2.x, f2.y, f2.z),
+                                   make_float3(f3.x, f3.y, f3.z), f2.w, v, w);
+    exact += 1;
+    if (d2 < b.d2) {
+        b.d2 = d2;
+        b.idx = idx;
+        b.v = v;
+        b.w = w;
+        dmin = sqrtf(d2);
+    }
+    return true;
+}
+
 // Scans at most `budget` entries of the list of the site whose record is
 // (sp, rg); if the list is not done by then, *resume is set to the next
 // entry (else -1).  The first st_cnt entries' spheres are read from LDS
@@ -379,36 +418,19 @@ __device__ __forceinline__ Best list_search(const DevMesh& m, const float3 q, co
 #pragma unroll
         for (int k = 0; k < kChunk; ++k) {
             if (e + k >= end) return e + k < stop;
-            // Sorted by ell = |s - c| - r: no later entry can beat d_min
-            // (triangle inequality).  ell is recomputed from (c, r) rather
-            // than loaded, which keeps the scan to one 16-byte load per
-            // entry.  The two terms are pulled apart by 1e-6 relative, more
-            // than the float32 rounding of the differences, the sum of
-            // squares, the square root and the subtraction together, so the
-            // value never exceeds the exact ell of the same float32 values
-            // by which the lists were sorted.
-            const float ux = sp.x - c[k].x, uy = sp.y - c[k].y, uz = sp.z - c[k].z;
-            const float ell = sqrtf(ux * ux + uy * uy + uz * uz) * (1.f - 1e-6f) - c[k].w * (1.f + 1e-6f);
-            if (ell - dqs >= dmin) {
+            const int64_t idx = e + k;
+            auto rec = [&](float4& f1, float4& f2, float4& f3) {
+                f1 = gload(m.list_rec + 3 * idx);
+                f2 = gload(m.list_rec + 3 * idx + 1);
+                f3 = gload(m.list_rec + 3 * idx + 2);
+                if (kCtr && tch.rec) tch.rec[idx] = 1;
+            };
+            unsigned long long ex = 0;
+            const bool go = scan_entry(q, sp, dqs, c[k], (int)idx, dmin, b, ex, rec);
+            if (kCtr) n.exact += ex;
+            if (!go) {
                 stop = e + k;
                 return false;
-            }
-            const float dx = q.x - c[k].x, dy = q.y - c[k].y, dz = q.z - c[k].z;
-            const float lim = dmin + c[k].w;
-            if (dx * dx + dy * dy + dz * dz >= lim * lim * 1.000001f) continue;
-            const int64_t idx = e + k;
-            const float4 f1 = gload(m.list_rec + 3 * idx), f2 = gload(m.list_rec + 3 * idx + 1), f3 = gload(m.list_rec + 3 * idx + 2);
-            if (kCtr && tch.rec) tch.rec[idx] = 1;
-            float v, w;
-            const float d2 = closest_point(q, make_float3(f1.x, f1.y, f1.z), make_float3(f2.x, f2.y, f2.z),
-                                           make_float3(f3.x, f3.y, f3.z), f2.w, v, w);
-            if (kCtr) n.exact += 1;
-            if (d2 < b.d2) {
-                b.d2 = d2;
-                b.idx = (int)idx;
-                b.v = v;
-                b.w = w;
-                dmin = sqrtf(d2);
             }
         }
         return true;
@@ -543,8 +565,11 @@ __device__ __noinline__ WaveScan list_search_wave(const float4* __restrict__ sit
             if (kCtr) exact += (unsigned)__popcll(__ballot(tested));
         }
         dmin = wave_min(dl);
+        // lane 63 loaded the chunk's last entry in its last slot (indices
+        // past the list's end are clamped to it): its ell decides the exit
         const int last = min(base + 64 * kWaveChunk, rg.w) - 1;
-        if (gload(list_rec + (3 * (int64_t)last)).w - dqs >= dmin) {
+        const float ell_last = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[kWaveChunk - 1].w), 63));
+        if (ell_last - dqs >= dmin) {
             end = last + 1;
             break;
         }
@@ -1552,6 +1577,185 @@ int64_t scan_scratch(int64_t n)
     return total + 1;
 }
 
+// ------------------------------------------------- search grouped by site
+// The search as three passes, for point sets that put many points in each
+// cell: locate every point (in the visiting order), sort the points by
+// located site, then scan each site's list once per group of lanes that
+// share it.  In the scan pass a wavefront holds 64 consecutive points of
+// the site order, so its lanes fall into a few runs of one site each.  For
+// each run the wavefront loads the site's list 64 entries at a time with
+// one coalesced load per lane (sphere and record) into LDS, and every lane
+// of the run scans its copy there, entry by entry in list order with the
+// same per-entry test (scan_entry) and budget as the per-lane scan: the
+// results are the plain kernel's, bit for bit.
+
+// Located site of each point in the visiting order: keys[j] = site (or
+// n_sites when the point is not finite, outside the domain box, or its walk
+// reached the step cap), pos[j] = j.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8)))
+locate_kernel(const DevMesh m, const FwdArgs a, uint32_t* __restrict__ keys, int32_t* __restrict__ pos)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const int64_t i = a.perm ? (int64_t)gload(a.perm + j) : j;
+    const int64_t iq = a.q_sorted ? j : i;
+    const float3 q = make_float3(gload(a.q + 3 * iq), gload(a.q + 3 * iq + 1), gload(a.q + 3 * iq + 2));
+    int s = -1;
+    if (isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && in_domain(m, q)) {
+        unsigned long long steps = 0, adj_read = 0, capped = 0;
+        if (m.oct) {
+            s = octree_locate(m, q, steps);
+        } else {
+            float4 sp;
+            int4 rg;
+            s = locate<false>(m, q, steps, adj_read, capped, Touch{}, sp, rg);
+        }
+    }
+    keys[j] = s >= 0 ? (uint32_t)s : (uint32_t)m.n_sites;
+    pos[j] = (int32_t)j;
+}
+
+// Entries of one shared chunk of a list in LDS: sphere, then the record.
+constexpr int kGroupChunk = 64;
+struct ChunkEntry {
+    float4 c, f1, f2, f3;
+};
+
+// Where each site's run starts and ends in the site-sorted order (runs[2k],
+// runs[2k + 1]; key n_sites, the points with no site, is run n_sites).  The
+// caller zeroes runs.
+__global__ void run_bounds_kernel(const uint32_t* __restrict__ keys, int64_t n, int32_t* __restrict__ runs)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t k = keys[j];
+    if (j == 0 || keys[j - 1] != k) runs[2 * (int64_t)k] = (int32_t)j;
+    if (j == n - 1 || keys[j + 1] != k) runs[2 * (int64_t)k + 1] = (int32_t)(j + 1);
+}
+
+// Work items per run: one per 64 points (the count, to be scanned).
+__global__ void run_items_kernel(const int32_t* __restrict__ runs, int64_t n_runs, uint32_t* __restrict__ items)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_runs) return;
+    items[k] = (uint32_t)((runs[2 * k + 1] - runs[2 * k] + kGroupChunk - 1) / kGroupChunk);
+}
+
+// The item list: item t = (first position, run).
+__global__ void item_list_kernel(const int32_t* __restrict__ runs, const uint32_t* __restrict__ item_off,
+                                 int64_t n_runs, int2* __restrict__ item)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_runs) return;
+    const int32_t b = runs[2 * k], e = runs[2 * k + 1];
+    uint32_t t = item_off[k];
+    for (int32_t p = b; p < e; p += kGroupChunk) item[t++] = make_int2(p, (int32_t)k);
+}
+
+// One wavefront per work item: up to 64 consecutive points of one run,
+// hence one site (or none: the points outside the domain box, not finite,
+// or whose walk reached the step cap).  Items past the last do nothing.
+template <bool kFused>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8)))
+grouped_kernel(const DevMesh m, const FwdArgs a, const int32_t* __restrict__ pos, const int2* __restrict__ item,
+               const uint32_t* __restrict__ n_items_p, const int32_t* __restrict__ runs)
+{
+    extern __shared__ __align__(16) int smem[];
+    const int nw = (int)(blockDim.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    ChunkEntry* chunk = (ChunkEntry*)smem + (threadIdx.x >> 6) * kGroupChunk;
+    int* acc_smem = smem + nw * kGroupChunk * (int)(sizeof(ChunkEntry) / sizeof(int));
+    const bool gv = kFused && a.grad_v;
+    const LdsAcc acc{gv ? a.grad_v : nullptr, acc_smem, (float*)(acc_smem + a.acc_slots), a.acc_slots};
+    if (gv) {
+        acc.init();
+        __syncthreads();
+    }
+    const int64_t t = (int64_t)blockIdx.x * nw + (threadIdx.x >> 6);
+    const bool live = t < (int64_t)gload(n_items_p);
+    int2 it = make_int2(0, -1);
+    if (live) it = gload(item + t);
+    const int run = __builtin_amdgcn_readfirstlane(it.y);
+    const int64_t j = (int64_t)it.x + lane;
+    const bool valid = live && j < (int64_t)gload(runs + (2 * (int64_t)(run < 0 ? 0 : run) + 1));
+    const int rs = run < m.n_sites ? run : -1;  // the run's site (uniform)
+    const int s = valid ? rs : -1;
+    int64_t i = 0;
+    float3 q = make_float3(0.f, 0.f, 0.f);
+    if (valid) {
+        const int64_t jj = gload(pos + j);
+        i = a.perm ? (int64_t)gload(a.perm + jj) : jj;
+        const int64_t iq = a.q_sorted ? jj : i;
+        q = make_float3(gload(a.q + 3 * iq), gload(a.q + 3 * iq + 1), gload(a.q + 3 * iq + 2));
+    }
+    const bool finite = valid && isfinite(q.x) && isfinite(q.y) && isfinite(q.z);
+    Best b{kInf, -1, 0.f, 0.f};
+    int resume = -1;
+    QueryCounts n;
+    if (live && rs >= 0) {
+        const float4 sp = gload(m.site_rec + 2 * rs);
+        const int4 rg = __builtin_bit_cast(int4, gload(m.site_rec + 2 * rs + 1));
+        float dqs = 0.f, dmin = kInf;
+        if (valid) {
+            const float wx = q.x - sp.x, wy = q.y - sp.y, wz = q.z - sp.z;
+            // |q - s| rounded up so that the early-exit bound stays conservative
+            dqs = sqrtf(wx * wx + wy * wy + wz * wz) * 1.000001f;
+        }
+        bool active = valid;
+        for (int base = rg.z; base < rg.w; base += kGroupChunk) {
+            if (__ballot(active) == 0ull) break;
+            if (base - rg.z >= kSerialBudget) {
+                // the same budget as the per-lane scan: the rest of the
+                // list goes to the wavefront-wide scan
+                if (active) resume = base;
+                break;
+            }
+            {
+                const int e = min(base + lane, rg.w - 1);
+                ChunkEntry ce;
+                ce.c = gload(m.list_sph + e);
+                ce.f1 = gload(m.list_rec + 3 * (int64_t)e);
+                ce.f2 = gload(m.list_rec + 3 * (int64_t)e + 1);
+                ce.f3 = gload(m.list_rec + 3 * (int64_t)e + 2);
+                chunk[lane] = ce;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (active) {
+                const int cnt = min(kGroupChunk, rg.w - base);
+                for (int k0 = 0; k0 < cnt && active; k0 += kChunk) {
+                    // kChunk spheres read ahead, then tested in list order
+                    float4 cc[kChunk];
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u) cc[u] = chunk[min(k0 + u, cnt - 1)].c;
+#pragma unroll
+                    for (int u = 0; u < kChunk; ++u) {
+                        if (!active || k0 + u >= cnt) break;
+                        const ChunkEntry* ce = &chunk[k0 + u];
+                        auto rec = [&](float4& f1, float4& f2, float4& f3) {
+                            f1 = ce->f1;
+                            f2 = ce->f2;
+                            f3 = ce->f3;
+                        };
+                        if (!scan_entry(q, sp, dqs, cc[u], base + k0 + u, dmin, b, n.exact, rec)) active = false;
+                    }
+                }
+            }
+            // every lane is done with the chunk before the next overwrites it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    finish_query<kFused, false>(m, valid, q, finite, s, b, resume, i, a.dist, a.tri, a.closest, a.grad_dist,
+                                a.grad_q, acc, nullptr, n, Touch{});
+    if (gv) {
+        __syncthreads();
+        acc.flush();
+    }
+}
+
 }  // namespace
 
 hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fused, bool counters,
@@ -1624,6 +1828,96 @@ size_t reorder_workspace_bytes(int64_t n, int bits)
     const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
     const int64_t nc = 256 * n_tiles;
     return sizeof(uint32_t) * (size_t)(4 * n + nc + scan_scratch(nc) + 64);
+}
+
+// Workspace of launch_grouped: the sort's (keys and positions, twice, and
+// the digit counts), then the runs (2 per site and one more), their item
+// counts and offsets (scanned with its scratch) and the item list.
+static size_t grouped_layout(int64_t n, int64_t n_sites, size_t* off_runs, size_t* off_cnt, size_t* off_tmp,
+                             size_t* off_items)
+{
+    const size_t sort_bytes = (reorder_workspace_bytes(n, 0) + 255) & ~(size_t)255;
+    const int64_t n_runs = n_sites + 1;
+    const int64_t max_items = n / kGroupChunk + n_runs + 1;
+    size_t o = sort_bytes;
+    *off_runs = o;
+    o += ((size_t)(2 * n_runs) * 4 + 255) & ~(size_t)255;
+    *off_cnt = o;
+    o += ((size_t)(n_runs + 1) * 4 + 255) & ~(size_t)255;
+    *off_tmp = o;
+    o += ((size_t)scan_scratch(n_runs + 1) * 4 + 255) & ~(size_t)255;
+    *off_items = o;
+    o += (size_t)max_items * 8;
+    return o;
+}
+
+size_t grouped_workspace_bytes(int64_t n, int64_t n_sites)
+{
+    size_t a, b, c, d;
+    return grouped_layout(n, n_sites, &a, &b, &c, &d);
+}
+
+hipError_t launch_grouped(const DevMesh& m, const FwdArgs& a, void* ws, bool fused, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    const int64_t n = a.n;
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t nc = 256 * n_tiles;
+    uint32_t* ka = (uint32_t*)ws;
+    int32_t* va = (int32_t*)(ka + n);
+    uint32_t* kb = (uint32_t*)(va + n);
+    int32_t* vb = (int32_t*)(kb + n);
+    uint32_t* counts = (uint32_t*)(vb + n);
+    uint32_t* tmp = counts + nc;
+    size_t o_runs, o_cnt, o_tmp, o_items;
+    grouped_layout(n, m.n_sites, &o_runs, &o_cnt, &o_tmp, &o_items);
+    int32_t* runs = (int32_t*)((char*)ws + o_runs);
+    uint32_t* cnt = (uint32_t*)((char*)ws + o_cnt);
+    uint32_t* stmp = (uint32_t*)((char*)ws + o_tmp);
+    int2* items = (int2*)((char*)ws + o_items);
+    const int64_t n_runs = (int64_t)m.n_sites + 1;
+    locate_kernel<<<grid_for(n, 256), 256, 0, st>>>(m, a, ka, va);
+    // sort by site (keys up to n_sites), 8 bits per pass, stable: within a
+    // site the points keep their visiting order
+    int key_bits = 1;
+    while (key_bits < 31 && ((int64_t)1 << key_bits) <= (int64_t)m.n_sites) ++key_bits;
+    uint32_t *kin = ka, *kout = kb;
+    int32_t *vin = va, *vout = vb;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        radix_upsweep<false><<<(unsigned)n_tiles, kSortBlock, 0, st>>>(m, a.q, kin, n, shift, 0, 0.f, 0.f, 0.f,
+                                                                       counts, n_tiles);
+        hipError_t e = exclusive_scan(counts, nc, tmp, st);
+        if (e != hipSuccess) return e;
+        radix_downsweep<false><<<(unsigned)n_tiles, kSortBlock, 0, st>>>(m, a.q, kin, vin, n, shift, 0, 0.f, 0.f,
+                                                                         0.f, counts, n_tiles, kout, vout, nullptr);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    // the runs of each site and the work items (a site's run in pieces of
+    // at most 64 points; the item count stays on the device)
+    fill_u32_kernel<<<grid_for(2 * n_runs, 256), 256, 0, st>>>((uint32_t*)runs, 0u, 2 * n_runs);
+    run_bounds_kernel<<<grid_for(n, 256), 256, 0, st>>>(kin, n, runs);
+    fill_u32_kernel<<<1, 1, 0, st>>>(cnt + n_runs, 0u, 1);
+    run_items_kernel<<<grid_for(n_runs, 256), 256, 0, st>>>(runs, n_runs, cnt);
+    hipError_t e = exclusive_scan(cnt, n_runs + 1, stmp, st);
+    if (e != hipSuccess) return e;
+    item_list_kernel<<<grid_for(n_runs, 256), 256, 0, st>>>(runs, cnt, n_runs, items);
+    FwdArgs args = a;
+    const int block = 256;
+    const int nw = block / 64;
+    const size_t chunk_bytes = (size_t)nw * kGroupChunk * sizeof(ChunkEntry);
+    size_t lds = chunk_bytes;
+    if (fused && a.grad_v) {
+        int slots = acc_slots_for(block);
+        while (slots > 64 && chunk_bytes + acc_lds_bytes(slots) > 65536) slots >>= 1;
+        args.acc_slots = slots;
+        lds += acc_lds_bytes(slots);
+    }
+    const int64_t max_items = n / kGroupChunk + n_runs + 1;
+    const unsigned grid = (unsigned)((max_items + nw - 1) / nw);
+    if (fused) grouped_kernel<true><<<grid, block, lds, st>>>(m, args, vin, items, cnt + n_runs, runs);
+    else grouped_kernel<false><<<grid, block, lds, st>>>(m, args, vin, items, cnt + n_runs, runs);
+    return hipGetLastError();
 }
 
 const int32_t* reorder_perm_location(void* ws, int64_t n, int bits)

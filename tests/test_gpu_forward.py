@@ -44,16 +44,18 @@ def test_c0_full(dev, c0):
 
 def test_c0_launch_configs_bitwise(dev, c0):
     c, m = c0
+    m.set_query_config(group=0)
     ref = run(dev, m, c["Q"])
-    for bs in (64, 512, 1024):
-        for reorder in (0, 1):
-            for xcd in (1, 3, 8):
-                for stage in (0, 1):
-                    m.set_query_config(block_size=bs, reorder=reorder, xcd_groups=xcd, stage=stage)
-                    out = run(dev, m, c["Q"])
-                    for a, b in zip(ref, out):
-                        assert np.array_equal(a, b, equal_nan=True), (bs, reorder, xcd, stage)
-    m.set_query_config(block_size=256, reorder=1, xcd_groups=1, stage=0)
+    for group in (0, 1):
+        for bs in (64, 512, 1024):
+            for reorder in (0, 1):
+                for xcd in (1, 3, 8):
+                    for stage in (0, 1):
+                        m.set_query_config(block_size=bs, reorder=reorder, xcd_groups=xcd, stage=stage, group=group)
+                        out = run(dev, m, c["Q"])
+                        for a, b in zip(ref, out):
+                            assert np.array_equal(a, b, equal_nan=True), (group, bs, reorder, xcd, stage)
+    m.set_query_config(block_size=256, reorder=1, xcd_groups=1, stage=0, group=2)
 
 
 @pytest.mark.parametrize("n", [1, 4095, 4097, 300_001])
@@ -81,20 +83,25 @@ def test_sort_points_is_a_permutation(dev, c0, n):
         assert np.median(step) < 0.1 * np.median(np.linalg.norm(qs - qs[::-1], axis=1))
 
 
+@pytest.mark.parametrize("group", [0, 1])
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 4097, 100_003])
-def test_ragged_sizes(dev, c0, n):
+def test_ragged_sizes(dev, c0, n, group):
     c, m = c0
     rng = np.random.default_rng(100 + n)
     Q = rng.uniform(-1.5, 1.5, (n, 3)).astype(np.float32)
+    m.set_query_config(group=group)
     d, t, cl = run(dev, m, Q)
+    m.set_query_config(group=2)
     assert d.shape == (n,)
     if n:
         idx = rng.choice(n, min(n, 3000), replace=False)
         check_forward(c["V"], c["F"], Q[idx], d[idx], t[idx], cl[idx], c["D"], label=f"n={n}")
 
 
-def test_special_points(dev, c0):
+@pytest.mark.parametrize("group", [0, 1])
+def test_special_points(dev, c0, group):
     c, m = c0
+    m.set_query_config(group=group)
     V, F = c["V"], c["F"]
     Q = np.concatenate([
         V[:40],                                             # exactly at vertices
@@ -108,6 +115,7 @@ def test_special_points(dev, c0):
     assert np.all(d[:40] <= 1e-5 * c["D"])
     Qn = np.array([[np.nan, 0, 0], [0, np.inf, 0], [-np.inf, 1, 1]], np.float32)
     d, t, cl = run(dev, m, Qn)
+    m.set_query_config(group=2)
     assert np.all(np.isnan(d)) and np.all(t == -1) and np.all(np.isnan(cl))
 
 
@@ -152,6 +160,11 @@ def test_c1_subset(dev, c1):
     c, m = c1
     d, t, cl = run(dev, m, c["Q"])
     print("C1 max|dd|/D, p99.9:", check_forward(c["V"], c["F"], c["Q"], d, t, cl, c["D"], label="C1"))
+    # the grouped search forced on (C1 has few points per site): the same bits
+    m.set_query_config(group=1)
+    d1, t1, cl1 = run(dev, m, c["Q"])
+    m.set_query_config(group=2)
+    assert np.array_equal(d, d1) and np.array_equal(t, t1) and np.array_equal(cl, cl1)
 
 
 def check_full_size(dev, c, m):
@@ -207,6 +220,29 @@ def test_c2_staging_is_exact(dev, c2):
     for key, o in outs.items():
         for a, b in zip(ref, o):
             assert torch.equal(a, b), key
+
+
+def test_c2_grouped_equals_one_pass(dev, c2):
+    """The grouped search (locate, sort by site, list chunks shared through
+    LDS) against the one-pass kernel on 2M points of C2, plain and fused
+    with dL/dV, both through the library's own sort and in a given order:
+    the same bits (dL/dV up to the order of float32 additions)."""
+    c, m = c2
+    q = torch.from_numpy(c["Q"][::5].copy()).cuda()
+    n = len(q)
+    g = torch.from_numpy(np.random.default_rng(82).normal(size=n).astype(np.float32)).cuda()
+    nv = len(c["V"])
+    outs = {}
+    for group in (0, 1):
+        m.set_query_config(group=group)
+        gv = torch.zeros((nv, 3), device="cuda")
+        outs[group] = dev.query(m, q) + dev.query_fused(m, q, g, grad_vertices=gv) + (gv,)
+    m.set_query_config(group=2)
+    torch.cuda.synchronize()
+    for a, b in zip(outs[0][:-1], outs[1][:-1]):
+        assert torch.equal(a, b)
+    gv0, gv1 = outs[0][-1], outs[1][-1]
+    assert (torch.linalg.norm(gv0 - gv1) / torch.linalg.norm(gv0)).item() <= 1e-5
 
 
 def test_c2_no_walk_reaches_the_step_cap(dev, c2):
