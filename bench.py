@@ -50,7 +50,7 @@ def kernel_source_hash():
 def load_traffic(kernel_hash, n_points):
     """HBM traffic of the search kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "search_kernel_c2_10M_traffic.json")
+    path = os.path.join(ROOT, "profiles", "search_c2_10M_traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
@@ -64,7 +64,7 @@ def load_traffic(kernel_hash, n_points):
 def load_limiter(kernel_hash, n_points):
     """What limits the search kernel, from the committed rocprofv3 pipeline
     counters, if they were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "search_kernel_c2_10M_pipeline.json")
+    path = os.path.join(ROOT, "profiles", "search_c2_10M_pipeline.json")
     try:
         with open(path) as f:
             t = json.load(f)
@@ -629,7 +629,7 @@ def main():
     kh = kernel_source_hash()
     # which search the library ran (p2m_query_config.group; 2 = automatic)
     grp = mesh.query_config()["group"]
-    grouped = grp == 1 or (grp == 2 and n >= 16 * st["n_sites"])
+    grouped = grp == 1 or (grp == 2 and n >= 48 * st["n_sites"])
     search_path = ("search phase of p2m_query_ordered: locate_kernel, sort by site, grouped_kernel "
                    "(list chunks shared through LDS)" if grouped else
                    "search phase of p2m_query_ordered: fwd_kernel (walk, regroup, per-lane list scans)")

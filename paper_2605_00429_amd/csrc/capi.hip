@@ -210,14 +210,15 @@ struct p2m_handle_ {
     // Whether a non-instrumented search of n points runs as the grouped
     // passes (locate, sort by site, shared list scans): config group = 1,
     // or automatic (2) for a forward (not fused) whose points average at
-    // least 16 per site, so that most wavefronts fill up with one site's
-    // points.  Measured on 10M points of the 327k-triangle mesh (61 per
-    // site): search 2.50 against 2.77 ms; fused, 3.81 against 3.68 ms.
+    // least 48 per site, so that most wavefronts fill up with one site's
+    // points.  Measured on the 327k-triangle mesh: 10M points (61 per
+    // site), search 2.50 against 2.77 ms; 4M near-surface points (24 per
+    // site), 1.41 against 1.11 ms; fused, 3.81 against 3.68 ms at 10M.
     bool grouped(int64_t n, bool fused) const
     {
         if (cfg.group == 0) return false;
         if (cfg.group == 1) return true;
-        return !fused && n >= 16 * (int64_t)H.n_sites;
+        return !fused && n >= 48 * (int64_t)H.n_sites;
     }
 
     // The search of `a` (sorted or not): the grouped passes or the one-pass
