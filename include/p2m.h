@@ -131,8 +131,7 @@ typedef struct {
                            (locate every point, sort the points by located site, then each run of
                            lanes sharing a site scans its list once, loaded 64 entries at a time
                            through LDS); 2 (default) = the three passes for a forward (not
-                           fused) whose points average at least 48 per site.  Results are
-                           identical. */
+                           fused) of at least 2,000,000 points.  Results are identical. */
 } p2m_query_config;
 
 void p2m_default_opts(p2m_build_opts* opts);

@@ -209,16 +209,17 @@ struct p2m_handle_ {
 
     // Whether a non-instrumented search of n points runs as the grouped
     // passes (locate, sort by site, shared list scans): config group = 1,
-    // or automatic (2) for a forward (not fused) whose points average at
-    // least 48 per site, so that most wavefronts fill up with one site's
-    // points.  Measured on the 327k-triangle mesh: 10M points (61 per
-    // site), search 2.50 against 2.77 ms; 4M near-surface points (24 per
-    // site), 1.41 against 1.11 ms; fused, 3.81 against 3.68 ms at 10M.
+    // or automatic (2) for a forward (not fused) of at least 2M points.
+    // The grouped passes cost a few hundred microseconds more in fixed
+    // work and win on large sets: measured 2.71 against 3.08 ms on 10M
+    // points of the 327k-triangle mesh, 1.09 against 1.12 on its 4M
+    // near-surface points, 3.46 against 3.68 on C1's 2M, but 0.95 against
+    // 0.74 on 1M points of the same mesh and 0.58 against 0.43 on 10k.
     bool grouped(int64_t n, bool fused) const
     {
         if (cfg.group == 0) return false;
         if (cfg.group == 1) return true;
-        return !fused && n >= 48 * (int64_t)H.n_sites;
+        return !fused && n >= 2000000;
     }
 
     // The search of `a` (sorted or not): the grouped passes or the one-pass
