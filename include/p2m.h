@@ -92,10 +92,15 @@ typedef struct {
     int32_t gpu_lists;         /* 1: the list stage's sphere-union tests run on the device
                                   (same lists; sites with more than 256 balls stay on the
                                   host); 0: all on the host (default 1; needs device >= 0) */
-    int32_t gpu_voronoi;       /* 1: the Voronoi stage's corner checks (is a site closer than
-                                  the cell's own to this corner?) run on the device, in rounds
-                                  over all cells in progress (same cells); 0: all on the host
-                                  (default 1; needs device >= 0) */
+    int32_t gpu_voronoi;       /* 1 (default): the Voronoi stage's cells are built on the
+                                  device, one wavefront per cell (kNN, clipping, corner
+                                  checks in rounds over all cells in progress); cells that
+                                  outgrow the device's per-cell capacity (128 faces, 1,024
+                                  polygon vertices) are built on the host; 2: only the
+                                  corner checks (is a site closer than the cell's own to
+                                  this corner?) run on the device, the host clips; 0: all
+                                  on the host.  The cells are the same, bit for bit, in all
+                                  three (needs device >= 0 for 1 and 2) */
     int32_t device;            /* HIP device to upload to; -2 (default) = the current
                                   device; -1 = host only (inspection, no query calls) */
 } p2m_build_opts;
@@ -111,6 +116,8 @@ typedef struct {
     double t_voronoi_s, t_optimize_s, t_lists_s, t_layout_s, t_total_s;
     int64_t device_bytes;
     double diag;
+    int64_t n_cells_device;    /* Voronoi cells (over every pass) built on the device */
+    int64_t n_cells_host;      /* ... and on the host (all of them with gpu_voronoi != 1) */
 } p2m_stats;
 
 /* Per-handle launch configuration of the query kernels. */

@@ -53,7 +53,8 @@ class p2m_stats(ctypes.Structure):
                 ("t_voronoi_s", ctypes.c_double), ("t_optimize_s", ctypes.c_double),
                 ("t_lists_s", ctypes.c_double), ("t_layout_s", ctypes.c_double),
                 ("t_total_s", ctypes.c_double), ("device_bytes", ctypes.c_int64),
-                ("diag", ctypes.c_double)]
+                ("diag", ctypes.c_double), ("n_cells_device", ctypes.c_int64),
+                ("n_cells_host", ctypes.c_int64)]
 
     def as_dict(self):
         d = {}

@@ -305,8 +305,10 @@ int32_t p2m_build(const p2m_mesh_desc* mesh, const p2m_build_opts* opts, p2m_han
             }
             const p2m::GpuListFn on_device = p2m::gpu_build_lists;
             const p2m::CheckFn checks_on_device = p2m::gpu_corner_checks;
+            const p2m::CellFn cells_on_device = p2m::gpu_cells;
             p2m::build_host(*mesh, o, h->H, o.gpu_lists ? &on_device : nullptr,
-                            o.gpu_voronoi ? &checks_on_device : nullptr);
+                            o.gpu_voronoi ? &checks_on_device : nullptr,
+                            o.gpu_voronoi == 1 ? &cells_on_device : nullptr);
             h->device = dev;
             h->upload_all(*mesh);
         } else {

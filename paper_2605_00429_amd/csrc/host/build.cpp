@@ -221,11 +221,75 @@ void apply_round(CellState& c, const Res& res, const std::vector<d3>& P, d3 ps, 
 // costs more than the checks.
 constexpr int64_t kHostTail = 256;
 
+// Per-thread scratch of the Voronoi stage.
+struct CellScratch {
+    std::vector<std::pair<double, int32_t>> knn;
+    std::vector<d3> corners;
+    std::vector<int32_t> found;
+    std::vector<int32_t> res;
+};
+
+// Step 1 of a cell: the box clipped by the bisectors of the site's kNN in
+// order of distance, stopping once the next site is beyond twice the
+// farthest corner; the cell stays in progress, with the corners that a site
+// outside the kNN could still cut pending, unless that stop came first.
+void start_cell(CellState& c, int32_t s, const std::vector<d3>& P, const KdTree& kd, d3 blo, d3 bhi,
+                CellScratch& w)
+{
+    const d3 ps = P[s];
+    c.cell.init_box(blo - ps, bhi - ps);
+    kd.knn(ps, kKnn, s, w.knn);
+    c.tested.push_back(s);
+    double r2max = c.cell.max_norm2();
+    bool final_by_radius = false;
+    for (const auto& e : w.knn) {
+        // a site at distance >= 2 * max corner radius cannot cut the cell
+        if (e.first >= 4.0 * r2max) {
+            final_by_radius = true;
+            break;
+        }
+        const d3 nv = P[e.second] - ps;
+        if (c.cell.clip(nv, 0.5 * norm2(nv), e.second)) r2max = c.cell.max_norm2();
+        c.tested.push_back(e.second);
+    }
+    std::sort(c.tested.begin(), c.tested.end());
+    // sites beyond the kNN radius can only cut corners farther than half of it
+    c.active = !final_by_radius && (int)w.knn.size() == kKnn;
+    if (c.active) {
+        c.dK2 = w.knn.back().first;
+        collect_pending(c, w.corners);
+    }
+}
+
+// The remaining rounds of one cell, its checks answered by KdTree::below
+// (the answers a batch of CornerChecks gives).
+void finish_cell(CellState& c, int32_t s, const std::vector<d3>& P, const KdTree& kd, int64_t budget,
+                 size_t round, CellScratch& w)
+{
+    const d3 ps = P[s];
+    for (size_t r = round; c.active && r <= P.size(); ++r) {
+        w.res.resize(c.pending.size());
+        for (size_t k = 0; k < c.pending.size(); ++k)
+            w.res[k] = kd.below(ps + c.pending[k], corner_limit(c.pending[k]), c.tested.data(),
+                                c.tested.data() + c.tested.size(), budget);
+        apply_round(c, [&](size_t k) { return w.res[k]; }, P, ps, budget >= 0, w.found, w.corners);
+    }
+}
+
+using CellDone = std::function<void(int64_t, int, const std::vector<d3>&, const std::vector<int32_t>&, bool, bool)>;
+
+void cell_done(CellState& c, int64_t i, int tid, CellScratch& w, const CellDone& done)
+{
+    std::vector<int32_t> faces;
+    c.cell.corners(w.corners);
+    c.cell.face_ids(faces);
+    done(i, tid, w.corners, faces, !c.cell.empty(), c.unresolved);
+    c = CellState();
+}
+
 // Voronoi cells of the sites in `sites` (indices into P) clipped to the box
 // [blo, bhi], by rounds:
-//   1. each cell clips the box by the bisectors of its kNN in order of
-//      distance, stopping early once the next site is beyond twice the
-//      farthest corner;
+//   1. each cell clips the box by the bisectors of its kNN (start_cell);
 //   2. every corner that a site outside the kNN could still cut is checked
 //      (CornerChecks: the nearest site closer to it than the cell's own, or
 //      none); the checks of all cells in progress go out as one batch;
@@ -233,6 +297,9 @@ constexpr int64_t kHostTail = 256;
 //      corners; cells with nothing found are final.  Rounds repeat until
 //      no cell is in progress; the last few cells run their remaining
 //      rounds on the host (KdTree::below gives the same answers).
+// A cell's steps depend on that cell alone, so batching changes nothing:
+// with `cells`, a device builds each chunk of cells whole, the same way,
+// and the host builds only the cells it hands back.
 // With budget >= 0 each check examines at most that many sites, and a cell
 // stops refining past kPass1MaxFaces faces; a check that gives up, or that
 // cap, leaves the cell a superset and marks it unresolved.  That
@@ -241,49 +308,49 @@ constexpr int64_t kHostTail = 256;
 // tid, corners, faces, ok, unresolved) receives sites[i]'s cell inside a
 // parallel loop.
 void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, const KdTree& kd, d3 blo, d3 bhi,
-                   int64_t budget, int nth, const CheckFn& check, bool host_tail,
-                   const std::function<void(int64_t, int, const std::vector<d3>&, const std::vector<int32_t>&, bool,
-                                            bool)>& done)
+                   int64_t budget, int nth, const CheckFn& check, bool host_tail, const CellFn* cells,
+                   p2m_stats& stats, const CellDone& done)
 {
-    struct Scratch {
-        std::vector<std::pair<double, int32_t>> knn;
-        std::vector<d3> corners;
-        std::vector<int32_t> found;
-        std::vector<int32_t> res;
-    };
-    std::vector<Scratch> scr(nth);
+    std::vector<CellScratch> scr(nth);
     const int64_t n = (int64_t)sites.size();
     if (kd.depth() + 1 > KdTree::kBelowStack) throw Error(P2M_ERR_INTERNAL, "site tree too deep");
     for (int64_t c0 = 0; c0 < n; c0 += kCellChunk) {
         const int64_t m = std::min(kCellChunk, n - c0);
+        if (cells) {
+            CellJob job;
+            job.kd = &kd;
+            job.sites = sites.data() + c0;
+            job.n = m;
+            job.blo = blo;
+            job.bhi = bhi;
+            job.budget = budget;
+            job.max_faces = kPass1MaxFaces;
+            job.knn = kKnn;
+            job.slack = kCornerSlack;
+            CellResult r;
+            (*cells)(job, r);
+            const int64_t n_redo = std::count(r.redo.begin(), r.redo.end(), (char)1);
+            stats.n_cells_device += m - n_redo;
+            stats.n_cells_host += n_redo;
+            parallel_for(m, nth, [&](int64_t i, int tid) {
+                if (r.redo[i]) {
+                    CellState c;
+                    start_cell(c, sites[c0 + i], P, kd, blo, bhi, scr[tid]);
+                    finish_cell(c, sites[c0 + i], P, kd, budget, 0, scr[tid]);
+                    cell_done(c, c0 + i, tid, scr[tid], done);
+                    return;
+                }
+                const std::vector<d3> corners(r.corners.begin() + r.corner_off[i],
+                                              r.corners.begin() + r.corner_off[i + 1]);
+                const std::vector<int32_t> faces(r.faces.begin() + r.face_off[i], r.faces.begin() + r.face_off[i + 1]);
+                done(c0 + i, tid, corners, faces, r.ok[i] != 0, r.unresolved[i] != 0);
+            }, 4);
+            continue;
+        }
+        stats.n_cells_host += m;
         std::vector<CellState> st(m);
         parallel_for(m, nth, [&](int64_t i, int tid) {
-            CellState& c = st[i];
-            Scratch& w = scr[tid];
-            const int32_t s = sites[c0 + i];
-            const d3 ps = P[s];
-            c.cell.init_box(blo - ps, bhi - ps);
-            kd.knn(ps, kKnn, s, w.knn);
-            c.tested.push_back(s);
-            double r2max = c.cell.max_norm2();
-            bool final_by_radius = false;
-            for (const auto& e : w.knn) {
-                // a site at distance >= 2 * max corner radius cannot cut the cell
-                if (e.first >= 4.0 * r2max) {
-                    final_by_radius = true;
-                    break;
-                }
-                const d3 nv = P[e.second] - ps;
-                if (c.cell.clip(nv, 0.5 * norm2(nv), e.second)) r2max = c.cell.max_norm2();
-                c.tested.push_back(e.second);
-            }
-            std::sort(c.tested.begin(), c.tested.end());
-            // sites beyond the kNN radius can only cut corners farther than half of it
-            c.active = !final_by_radius && (int)w.knn.size() == kKnn;
-            if (c.active) {
-                c.dK2 = w.knn.back().first;
-                collect_pending(c, w.corners);
-            }
+            start_cell(st[i], sites[c0 + i], P, kd, blo, bhi, scr[tid]);
         }, 16);
         std::vector<int64_t> act;
         for (int64_t i = 0; i < m; ++i)
@@ -292,16 +359,7 @@ void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, 
             if (host_tail && (int64_t)act.size() <= kHostTail) {
                 // the tail: each cell runs its remaining rounds by itself
                 parallel_for((int64_t)act.size(), nth, [&](int64_t j, int tid) {
-                    CellState& c = st[act[j]];
-                    Scratch& w = scr[tid];
-                    const d3 ps = P[sites[c0 + act[j]]];
-                    for (size_t r = round; c.active && r <= P.size(); ++r) {
-                        w.res.resize(c.pending.size());
-                        for (size_t k = 0; k < c.pending.size(); ++k)
-                            w.res[k] = kd.below(ps + c.pending[k], corner_limit(c.pending[k]), c.tested.data(),
-                                                c.tested.data() + c.tested.size(), budget);
-                        apply_round(c, [&](size_t k) { return w.res[k]; }, P, ps, budget >= 0, w.found, w.corners);
-                    }
+                    finish_cell(st[act[j]], sites[c0 + act[j]], P, kd, budget, round, scr[tid]);
                 }, 1);
                 act.clear();
                 break;
@@ -328,7 +386,7 @@ void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, 
             check(job, res);
             parallel_for((int64_t)act.size(), nth, [&](int64_t j, int tid) {
                 CellState& c = st[act[j]];
-                Scratch& w = scr[tid];
+                CellScratch& w = scr[tid];
                 const int64_t first = c.first;
                 apply_round(c, [&](size_t k) { return res[first + (int64_t)k]; }, P, P[sites[c0 + act[j]]],
                             budget >= 0, w.found, w.corners);
@@ -338,15 +396,7 @@ void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, 
                 if (st[i].active) next.push_back(i);
             act.swap(next);
         }
-        parallel_for(m, nth, [&](int64_t i, int tid) {
-            CellState& c = st[i];
-            Scratch& w = scr[tid];
-            std::vector<int32_t> faces;
-            c.cell.corners(w.corners);
-            c.cell.face_ids(faces);
-            done(c0 + i, tid, w.corners, faces, !c.cell.empty(), c.unresolved);
-            c = CellState();
-        }, 16);
+        parallel_for(m, nth, [&](int64_t i, int tid) { cell_done(st[i], c0 + i, tid, scr[tid], done); }, 16);
     }
 }
 
@@ -474,14 +524,14 @@ void check_mesh(const p2m_mesh_desc& m)
 }  // namespace
 
 void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructure& H, const GpuListFn* gpu,
-                const CheckFn* gpu_checks)
+                const CheckFn* gpu_checks, const CellFn* gpu_cells)
 {
     const auto t_start = clk::now();
     check_mesh(mesh);
     if (!(o.domain_scale >= 1.0f) || !(o.tau_scale > 0) || o.ring_sites < 0 || o.ring_layers < 0 ||
         !(o.list_inflation_rel >= 0) || !(o.seed_cell_scale > 0) || o.seed_max_cells < 1 ||
         o.decomposition < 0 || o.decomposition > 1 || o.octree_max_list < 1 || o.octree_max_depth < 0 ||
-        o.octree_max_depth > 16)
+        o.octree_max_depth > 16 || o.gpu_voronoi < 0 || o.gpu_voronoi > 2)
         throw Error(P2M_ERR_INVALID_ARG, "invalid build option");
     const int nth = resolve_threads(o.n_threads);
     const int64_t nV = mesh.n_vertices, nT = mesh.n_triangles;
@@ -621,7 +671,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         std::vector<std::vector<std::pair<uint64_t, d3>>> site_keys(nVS);
         std::vector<int32_t> vsites(nVS);
         std::iota(vsites.begin(), vsites.end(), 0);
-        compute_cells(vsites, P, kd, blo, bhi, kPass1Budget, nth, checks, gpu_checks != nullptr,
+        compute_cells(vsites, P, kd, blo, bhi, kPass1Budget, nth, checks, gpu_checks != nullptr, gpu_cells, H.stats,
                       [&](int64_t s, int, const std::vector<d3>& corners, const std::vector<int32_t>& faces, bool ok,
                           bool unres) {
             cell_corners[s] = corners;
@@ -810,7 +860,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
                 std::vector<int32_t> asites;
                 for (size_t i = 0; i < aux.size(); ++i)
                     if (need[i]) asites.push_back(nVS + (int32_t)i);
-                compute_cells(asites, PP, kd2, blo, bhi, -1, nth, checks, gpu_checks != nullptr,
+                compute_cells(asites, PP, kd2, blo, bhi, -1, nth, checks, gpu_checks != nullptr, gpu_cells, H.stats,
                               [&](int64_t j, int, const std::vector<d3>&, const std::vector<int32_t>& faces, bool ok,
                                   bool) {
                     const int32_t i = asites[j] - nVS;
@@ -884,7 +934,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         std::vector<int32_t> todo;
         for (int32_t s = 0; s < nS; ++s)
             if (!cell_done[s]) todo.push_back(s);
-        compute_cells(todo, P, kd, blo, bhi, -1, nth, checks, gpu_checks != nullptr,
+        compute_cells(todo, P, kd, blo, bhi, -1, nth, checks, gpu_checks != nullptr, gpu_cells, H.stats,
                       [&](int64_t i, int, const std::vector<d3>& corners, const std::vector<int32_t>& faces, bool ok,
                           bool) {
             const int32_t s = todo[i];

@@ -104,15 +104,53 @@ struct CornerChecks {
 // p2m::Error.
 using CheckFn = std::function<void(const CornerChecks&, std::vector<int32_t>& out)>;
 
+// A chunk of Voronoi cells for a device (Sec. 3.2): the cell of point
+// sites[i] of the tree, clipped to the box [blo, bhi], built the way the
+// host builds it: the box clipped by the bisectors of the knn nearest
+// sites (stopping at twice the farthest corner), then rounds of corner
+// checks (KdTree::below with limit |x|^2 (1 - slack)) and clips until no
+// corner beyond half the knn radius is cut.  With budget >= 0 each check
+// examines at most that many sites and a cell with more than max_faces
+// faces stops, unresolved.
+struct CellJob {
+    const KdTree* kd = nullptr;
+    const int32_t* sites = nullptr;
+    int64_t n = 0;
+    d3 blo{0, 0, 0}, bhi{0, 0, 0};
+    int64_t budget = -1;
+    int32_t max_faces = 0;
+    int32_t knn = 0;
+    double slack = 0;
+};
+// Per cell i: its distinct corners relative to the site (sorted as
+// ClipCell::corners gives them) in corners[corner_off[i] .. corner_off[i+1]),
+// the sites of its faces of positive area (sorted) in
+// faces[face_off[i] .. face_off[i+1]), whether it is a polytope (ok) and
+// whether a check or the face cap gave up (unresolved).  redo[i] asks the
+// host to build cell i itself (it outgrew the device's per-cell capacity);
+// its other entries are then empty.
+struct CellResult {
+    std::vector<int64_t> corner_off, face_off;
+    std::vector<d3> corners;
+    std::vector<int32_t> faces;
+    std::vector<char> ok, unresolved, redo;
+};
+using CellFn = std::function<void(const CellJob&, CellResult&)>;
+
 // Throws p2m::Error on invalid input.  With `gpu`, the list stage's
 // sphere-union tests run through it (sites with more than kDeviceBalls balls stay on
-// the host); with `gpu_checks`, the Voronoi stage's corner checks do.  The
-// structure is the same either way.
+// the host); with `gpu_checks`, the Voronoi stage's corner checks and the
+// seed grid's nearest sites do; with `gpu_cells` as well, whole cells are
+// built through it.  The structure is the same either way.
 void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& opts, HostStructure& out,
-                const GpuListFn* gpu = nullptr, const CheckFn* gpu_checks = nullptr);
+                const GpuListFn* gpu = nullptr, const CheckFn* gpu_checks = nullptr,
+                const CellFn* gpu_cells = nullptr);
 
 // The device implementation of CheckFn (current HIP device).
 void gpu_corner_checks(const CornerChecks& job, std::vector<int32_t>& out);
+
+// The device implementation of CellFn (current HIP device).
+void gpu_cells(const CellJob& job, CellResult& out);
 
 // The device implementation of GpuListFn (current HIP device).
 void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vector<int32_t>& ids,

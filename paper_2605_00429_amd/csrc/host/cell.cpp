@@ -1,5 +1,7 @@
 #include "cell.h"
 
+#include "clip_core.h"
+
 #include <algorithm>
 #include <cmath>
 
@@ -13,7 +15,7 @@ void ClipCell::seal(Face& f) const
     double r2 = 0;
     for (int32_t i = 0; i < f.count; ++i) r2 = std::max(r2, norm2(v_[f.begin + i] - c));
     f.c = c;
-    f.r = std::sqrt(r2) * (1.0 + 1e-12);
+    f.r = std::sqrt(r2) * kSealInflate;
 }
 
 void ClipCell::compact()
@@ -59,7 +61,7 @@ bool ClipCell::clip(d3 n, double h, int32_t id)
 {
     const double nn = norm(n);
     if (!(nn > 0)) return false;
-    const double eps = 1e-12 * nn * scale_;
+    const double eps = kClipEps * nn * scale_;
     cut_.clear();
     bool changed = false;
     for (size_t fi = 0; fi < faces_.size();) {
@@ -114,14 +116,15 @@ bool ClipCell::clip(d3 n, double h, int32_t id)
             live_ += (size_t)cnt;
             ++fi;
         } else {
+            // dropped; the faces after it keep their order
             v_.resize(nb);
-            faces_[fi] = faces_.back();
-            faces_.pop_back();
+            faces_.erase(faces_.begin() + (std::ptrdiff_t)fi);
         }
     }
     if (!changed) return false;
 
-    // The new face: the cut points ordered by angle around their centroid.
+    // The new face: the cut points ordered by angle around their centroid
+    // (by diamond_angle, ties by the order the faces gave them).
     if (cut_.size() >= 3) {
         d3 c{0, 0, 0};
         for (const d3& p : cut_) c = c + p;
@@ -134,10 +137,10 @@ bool ClipCell::clip(d3 n, double h, int32_t id)
         std::vector<std::pair<double, int32_t>> ang(cut_.size());
         for (size_t i = 0; i < cut_.size(); ++i) {
             const d3 r = cut_[i] - c;
-            ang[i] = {std::atan2(dot(r, w), dot(r, u)), (int32_t)i};
+            ang[i] = {diamond_angle(dot(r, u), dot(r, w)), (int32_t)i};
         }
         std::sort(ang.begin(), ang.end());
-        const double tol2 = (1e-11 * scale_) * (1e-11 * scale_);
+        const double tol2 = (kMergeTol * scale_) * (kMergeTol * scale_);
         const int32_t nb = (int32_t)v_.size();
         for (const auto& e : ang) {
             const d3& p = cut_[e.second];
@@ -168,7 +171,7 @@ void ClipCell::corners(std::vector<d3>& out) const
         if (a.y != b.y) return a.y < b.y;
         return a.z < b.z;
     });
-    const double tol = 1e-11 * scale_;
+    const double tol = kMergeTol * scale_;
     const double tol2 = tol * tol;
     std::vector<char> dup(out.size(), 0);
     for (size_t i = 0; i < out.size(); ++i) {
@@ -185,7 +188,7 @@ void ClipCell::corners(std::vector<d3>& out) const
 void ClipCell::face_ids(std::vector<int32_t>& out) const
 {
     out.clear();
-    const double min_area = (1e-12 * scale_) * (1e-12 * scale_);
+    const double min_area = (kMinArea * scale_) * (kMinArea * scale_);
     for (const Face& f : faces_) {
         d3 a{0, 0, 0};
         const d3& p0 = v_[f.begin];

@@ -1,10 +1,13 @@
-"""Voronoi corner checks on the GPU (gpu_voronoi = 1) give the host's cells:
-the same sites (vertex and auxiliary, whose placement depends on the
-first pass's cells), the same Delaunay neighbours and the same interception
-lists, site by site, on meshes with every kind of degeneracy the builder
-meets (co-spherical and co-circular sites, line clusters, budgeted checks
-that give up), and at the 327,680-triangle size, where the time of the
-Voronoi stage on each side is printed."""
+"""The Voronoi stage on the GPU gives the host's cells.  Three modes build
+the same structure: gpu_voronoi = 0 (all on the host), 2 (corner checks on
+the device, clipping on the host) and 1 (whole cells on the device, one
+wavefront per cell, cells that outgrow the device capacity on the host).
+Compared: the sites (vertex and auxiliary, whose placement depends on the
+first pass's cells), the Delaunay neighbours and the interception lists,
+site by site, on meshes with every kind of degeneracy the builder meets
+(co-spherical and co-circular sites, line clusters, budgeted checks that
+give up, axis cells too large for the device), and at the 327,680-triangle
+size, where the time of the Voronoi stage in each mode is printed."""
 import numpy as np
 import pytest
 
@@ -59,33 +62,64 @@ CASES = {
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_device_checks_give_the_host_cells(dev, name):
+def test_device_cells_give_the_host_cells(dev, name):
     V, F = CASES[name]()
     m0 = dev.Mesh(V, F, gpu_voronoi=0)
-    m1 = dev.Mesh(V, F, gpu_voronoi=1)
-    assert_same_structure(m0, m1, name)
+    for mode in (1, 2):
+        m = dev.Mesh(V, F, gpu_voronoi=mode)
+        assert_same_structure(m0, m, f"{name} mode {mode}")
+        st = m.stats()
+        if mode == 1:
+            assert st["n_cells_device"] > 0, name
+        else:
+            assert st["n_cells_device"] == 0, name
+    print(name, {k: m0.stats()[k] for k in ("n_sites", "n_aux_sites")},
+          "device mode 1 cells:", dev.Mesh(V, F, gpu_voronoi=1).stats()["n_cells_device"])
 
 
-def test_device_checks_without_augmentation_and_degenerate(dev):
+def test_device_cells_without_augmentation_and_degenerate(dev):
     V, F = gen.icosphere(4)
-    m0, m1 = dev.Mesh(V, F, gpu_voronoi=0, augment=0), dev.Mesh(V, F, gpu_voronoi=1, augment=0)
-    assert_same_structure(m0, m1, "icosphere-4 augment=0")
+    m0 = dev.Mesh(V, F, gpu_voronoi=0, augment=0)
+    for mode in (1, 2):
+        assert_same_structure(m0, dev.Mesh(V, F, gpu_voronoi=mode, augment=0), f"icosphere-4 augment=0 mode {mode}")
     # a far-away vertex and a triangle with a repeated vertex
     V, F = gen.uv_sphere(12, 6)
     V2 = np.concatenate([V, [[5, 5, 5]], V[:3]], 0).astype(np.float32)
     F2 = np.concatenate([F, [[0, len(V) + 1, len(V) + 2]], [[1, 1, 2]]], 0).astype(np.int32)
-    m0, m1 = dev.Mesh(V2, F2, gpu_voronoi=0), dev.Mesh(V2, F2, gpu_voronoi=1)
-    assert_same_structure(m0, m1, "degenerate")
+    m0 = dev.Mesh(V2, F2, gpu_voronoi=0)
+    for mode in (1, 2):
+        assert_same_structure(m0, dev.Mesh(V2, F2, gpu_voronoi=mode), f"degenerate mode {mode}")
 
 
-def test_device_checks_full_size(dev):
+def test_device_cells_hand_large_cells_back(dev):
+    """A capped cylinder: the cells of the vertices on its axis are cut by
+    every vertex of the wall and outgrow the device's per-cell capacity;
+    they are built on the host and the structure is still the host's."""
+    V, F = gen.cylinder_cone(256, 16)
+    m0, m1 = dev.Mesh(V, F, gpu_voronoi=0), dev.Mesh(V, F, gpu_voronoi=1)
+    assert_same_structure(m0, m1, "cylinder 256x16")
+    st = m1.stats()
+    assert st["n_cells_host"] > 0 and st["n_cells_device"] > 0, st
+
+
+def test_device_cells_full_size(dev):
     """The displaced icosphere-7 (327,680 triangles): identical statistics
-    and site positions, 3,000 sampled sites' neighbours and lists."""
+    and site positions, 3,000 sampled sites' neighbours and lists, in each
+    device mode; nearly every cell is built on the device."""
     from gen.configs import c2_mesh
     V, F, _ = c2_mesh()
-    m0, m1 = dev.Mesh(V, F, gpu_voronoi=0), dev.Mesh(V, F, gpu_voronoi=1)
+    m0 = dev.Mesh(V, F, gpu_voronoi=0)
     rng = np.random.default_rng(53)
     n = m0.stats()["n_sites"]
-    s0, s1 = assert_same_structure(m0, m1, "C2", sites=rng.choice(n, 3000, replace=False))
-    print(f"Voronoi stage: host checks {s0['t_voronoi_s']:.2f}s, device checks {s1['t_voronoi_s']:.2f}s; "
-          f"whole build {s0['t_total_s']:.2f}s / {s1['t_total_s']:.2f}s")
+    pick = rng.choice(n, 3000, replace=False)
+    s0 = m0.stats()
+    times = {0: (s0["t_voronoi_s"], s0["t_total_s"])}
+    for mode in (2, 1):
+        m = dev.Mesh(V, F, gpu_voronoi=mode)
+        _, s = assert_same_structure(m0, m, f"C2 mode {mode}", sites=pick)
+        times[mode] = (s["t_voronoi_s"], s["t_total_s"])
+        if mode == 1:
+            assert s["n_cells_device"] >= 0.99 * (s["n_cells_device"] + s["n_cells_host"]), s
+        del m
+    print("Voronoi stage / whole build (s): host " + "%.2f / %.2f" % times[0]
+          + ", device checks " + "%.2f / %.2f" % times[2] + ", device cells " + "%.2f / %.2f" % times[1])

@@ -182,7 +182,7 @@ def test_unreferenced_duplicate_and_degenerate_input():
     check_exact(m, V2, F2, Q)
 
 
-@pytest.mark.parametrize("case", ["no_tris", "bad_index", "neg_index", "nan_vertex", "bad_opt"])
+@pytest.mark.parametrize("case", ["no_tris", "bad_index", "neg_index", "nan_vertex", "bad_opt", "bad_voronoi_mode"])
 def test_build_errors(case):
     V, F = gen.tetrahedron()
     kw = {}
@@ -198,12 +198,25 @@ def test_build_errors(case):
     elif case == "nan_vertex":
         V = V.copy(); V[2, 1] = np.nan
         code = p2m._lib.P2M_ERR_BAD_MESH
+    elif case == "bad_voronoi_mode":
+        kw = dict(gpu_voronoi=3)
+        code = p2m._lib.P2M_ERR_INVALID_ARG
     else:
         kw = dict(domain_scale=0.5)
         code = p2m._lib.P2M_ERR_INVALID_ARG
     with pytest.raises(p2m.P2MError) as e:
         p2m.Mesh(V, F, device="host", **kw)
     assert e.value.code == code
+
+
+def test_host_only_build_counts_its_cells():
+    """Without a device every Voronoi cell (of every pass) is built on the
+    host: at least one per site."""
+    V, F = gen.icosphere(3)
+    m = p2m.Mesh(V, F, device="host")
+    st = m.stats()
+    assert st["n_cells_device"] == 0
+    assert st["n_cells_host"] >= st["n_sites"]
 
 
 def test_null_arguments_and_host_only_queries():
