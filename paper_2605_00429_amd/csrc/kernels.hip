@@ -363,7 +363,9 @@ constexpr int kChunk = 4;
 // relative, more than the float32 rounding of the differences, the sum of
 // squares, the square root and the subtraction together, so the value never
 // exceeds the exact ell of the same float32 values by which the lists were
-// sorted.  An entry past the sphere prune is tested exactly with its record
+// sorted.  That margin also covers the hardware square root (within 1 ulp),
+// one instruction where the correctly rounded one takes about sixteen, on
+// every entry scanned.  An entry past the sphere prune is tested exactly with its record
 // (rec(f1, f2, f3): first vertex and ell, first edge and e1.e2, second
 // edge and id).  Both scans (per lane, and per group of lanes sharing a
 // site) run this one function, so they decide alike.
@@ -373,7 +375,7 @@ __device__ __forceinline__ bool scan_entry(const float3 q, const float4 sp, cons
                                            Rec rec)
 {
     const float ux = sp.x - c.x, uy = sp.y - c.y, uz = sp.z - c.z;
-    const float ell = sqrtf(ux * ux + uy * uy + uz * uz) * (1.f - 1e-6f) - c.w * (1.f + 1e-6f);
+    const float ell = __builtin_amdgcn_sqrtf(ux * ux + uy * uy + uz * uz) * (1.f - 1e-6f) - c.w * (1.f + 1e-6f);
     if (ell - dqs >= dmin) return false;
     const float dx = q.x - c.x, dy = q.y - c.y, dz = q.z - c.z;
     const float lim = dmin + c.w;
