@@ -209,17 +209,20 @@ struct p2m_handle_ {
 
     // Whether a non-instrumented search of n points runs as the grouped
     // passes (locate, sort by site, shared list scans): config group = 1,
-    // or automatic (2) for a forward (not fused) of at least 2M points.
-    // The grouped passes cost a few hundred microseconds more in fixed
-    // work and win on large sets: measured 2.71 against 3.08 ms on 10M
-    // points of the 327k-triangle mesh, 1.09 against 1.12 on its 4M
-    // near-surface points, 3.46 against 3.68 on C1's 2M, but 0.95 against
-    // 0.74 on 1M points of the same mesh and 0.58 against 0.43 on 10k.
+    // or automatic (2) for a forward of at least 2M points and a fused
+    // call of at least 8M.  The grouped passes cost a few hundred
+    // microseconds more in fixed work and win on large sets: forwards
+    // measured 2.59 against 3.05 ms on 10M points of the 327k-triangle
+    // mesh, 1.03 against 1.07 on its 4M near-surface points, 3.37 against
+    // 3.69 on C1's 2M, but 0.89 against 0.74 on 1M points of the same mesh
+    // and 0.57 against 0.40 on 10k; fused calls 3.59 against 3.68 ms on
+    // the 10M points but 1.43 against 1.32 on the 4M and 3.96 against
+    // 3.83 on C1.
     bool grouped(int64_t n, bool fused) const
     {
         if (cfg.group == 0) return false;
         if (cfg.group == 1) return true;
-        return !fused && n >= 2000000;
+        return n >= (fused ? 8000000 : 2000000);
     }
 
     // The search of `a` (sorted or not): the grouped passes or the one-pass
