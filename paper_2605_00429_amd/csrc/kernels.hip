@@ -63,28 +63,32 @@ __device__ __forceinline__ float closest_point(const float3 q, const float3 a, c
     const float den = va + vb + vc;
     const float e43 = d4 - d3, e56 = d5 - d6;
     // face region, then each edge / vertex region in increasing priority
+    // every candidate computed, then selected: no branches (an unselected
+    // reciprocal may be inf or NaN and is discarded)
     const float inv = __builtin_amdgcn_rcpf(den);
+    const float t_bc = e43 * __builtin_amdgcn_rcpf(e43 + e56);
+    const float t_ca = d2 * __builtin_amdgcn_rcpf(d2 - d6);
+    const float t_ab = d1 * __builtin_amdgcn_rcpf(d1 - d3);
+    const bool r_bc = va <= 0.f && e43 >= 0.f && e56 >= 0.f;  // edge bc
+    const bool r_ca = vb <= 0.f && d2 >= 0.f && d6 <= 0.f;    // edge ca
+    const bool r_c = d6 >= 0.f && d5 <= d6;                   // vertex c
+    const bool r_ab = vc <= 0.f && d1 >= 0.f && d3 <= 0.f;    // edge ab
+    const bool r_b = d3 >= 0.f && d4 <= d3;                   // vertex b
+    const bool r_a = d1 <= 0.f && d2 <= 0.f;                  // vertex a
     float vv = vb * inv, ww = vc * inv;
-    bool face = true;
-    if (va <= 0.f && e43 >= 0.f && e56 >= 0.f) {  // edge bc
-        const float t = e43 * __builtin_amdgcn_rcpf(e43 + e56);
-        vv = 1.f - t; ww = t; face = false;
-    }
-    if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {    // edge ca
-        vv = 0.f; ww = d2 * __builtin_amdgcn_rcpf(d2 - d6); face = false;
-    }
-    if (d6 >= 0.f && d5 <= d6) {                  // vertex c
-        vv = 0.f; ww = 1.f; face = false;
-    }
-    if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {    // edge ab
-        vv = d1 * __builtin_amdgcn_rcpf(d1 - d3); ww = 0.f; face = false;
-    }
-    if (d3 >= 0.f && d4 <= d3) {                  // vertex b
-        vv = 1.f; ww = 0.f; face = false;
-    }
-    if (d1 <= 0.f && d2 <= 0.f) {                 // vertex a
-        vv = 0.f; ww = 0.f; face = false;
-    }
+    vv = r_bc ? 1.f - t_bc : vv;
+    ww = r_bc ? t_bc : ww;
+    vv = r_ca ? 0.f : vv;
+    ww = r_ca ? t_ca : ww;
+    vv = r_c ? 0.f : vv;
+    ww = r_c ? 1.f : ww;
+    vv = r_ab ? t_ab : vv;
+    ww = r_ab ? 0.f : ww;
+    vv = r_b ? 1.f : vv;
+    ww = r_b ? 0.f : ww;
+    vv = r_a ? 0.f : vv;
+    ww = r_a ? 0.f : ww;
+    const bool face = !(r_bc || r_ca || r_c || r_ab || r_b || r_a);
     const bool flat = !(den > 0.f && den < kInf);
     if (face && flat) {
         // zero-area triangle: best of its three edges (rare)
