@@ -1151,7 +1151,14 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
-void gpu_cells(const CellJob& job, CellResult& out)
+namespace {
+
+// Cells per device pass: each holds a 118 KB slab, so a pass needs at most
+// about 1.9 GB of device memory.
+constexpr int64_t kDevCells = 16384;
+
+// gpu_cells for one pass of at most kDevCells cells.
+void cells_pass(const CellJob& job, CellResult& out)
 {
     const int64_t m = job.n;
     out.corner_off.assign(m + 1, 0);
@@ -1196,7 +1203,7 @@ void gpu_cells(const CellJob& job, CellResult& out)
     const size_t o_off = carve(sizeof(int64_t) * (m + 1));
     const size_t o_foff = carve(sizeof(int64_t) * (m + 1));
     DevBuf mem;
-    check(hipMalloc(&mem.p, total), "hipMalloc (device cells)");
+    check(hipMalloc(&mem.p, total), "hipMalloc (device cells; gpu_voronoi = 0 or 2 build the cells with less device memory)");
     char* base = (char*)mem.p;
     CellMem M;
     M.hdr = (CellHdr*)(base + o_hdr);
@@ -1292,6 +1299,40 @@ void gpu_cells(const CellJob& job, CellResult& out)
                   "hipMemcpy (device cells)");
     if (nf) check(hipMemcpy(out.faces.data(), d_faces.p, sizeof(int32_t) * nf, hipMemcpyDeviceToHost),
                   "hipMemcpy (device cells)");
+}
+
+}  // namespace
+
+void gpu_cells(const CellJob& job, CellResult& out)
+{
+    if (job.n <= kDevCells) {
+        cells_pass(job, out);
+        return;
+    }
+    out.corner_off.assign(1, 0);
+    out.face_off.assign(1, 0);
+    out.corners.clear();
+    out.faces.clear();
+    out.ok.clear();
+    out.unresolved.clear();
+    out.redo.clear();
+    for (int64_t c0 = 0; c0 < job.n; c0 += kDevCells) {
+        CellJob part = job;
+        part.sites = job.sites + c0;
+        part.n = std::min(kDevCells, job.n - c0);
+        CellResult r;
+        cells_pass(part, r);
+        const int64_t cb = out.corner_off.back(), fb = out.face_off.back();
+        for (int64_t i = 0; i < part.n; ++i) {
+            out.corner_off.push_back(cb + r.corner_off[i + 1]);
+            out.face_off.push_back(fb + r.face_off[i + 1]);
+        }
+        out.corners.insert(out.corners.end(), r.corners.begin(), r.corners.end());
+        out.faces.insert(out.faces.end(), r.faces.begin(), r.faces.end());
+        out.ok.insert(out.ok.end(), r.ok.begin(), r.ok.end());
+        out.unresolved.insert(out.unresolved.end(), r.unresolved.begin(), r.unresolved.end());
+        out.redo.insert(out.redo.end(), r.redo.begin(), r.redo.end());
+    }
 }
 
 }  // namespace p2m
