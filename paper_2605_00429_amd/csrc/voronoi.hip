@@ -46,20 +46,32 @@ constexpr int kBlock = 256;
 // 32 for any int32 site count.
 constexpr int kMaxStack = 32;
 
+// The site kd-tree as the device reads it: one 64-byte record per node (its
+// box and its links together, so a visit is one load), and the points in
+// leaf order with their ids (a leaf's points are contiguous).
+struct DevNode {
+    double lo[3], hi[3];
+    int32_t begin, end, left, right;  // point range in leaf order; left = -1 for a leaf
+};
+struct DevLeafPt {
+    double x, y, z;
+    int32_t id, pad;
+};
+static_assert(sizeof(DevNode) == 64 && sizeof(DevLeafPt) == 32, "tree records");
+
 struct KdView {
-    const double* box;     // 6 per node: lo xyz, hi xyz
-    const int4* link;      // per node: begin, end, left (-1 for a leaf), right
-    const int32_t* order;  // leaf ranges index this
-    const double* pts;     // 3 per site
+    const DevNode* node;
+    const DevLeafPt* leaf;  // leaf[k]: the point at position k of the leaf order
+    const double* pts;      // 3 per site, by id
 };
 
 // Squared distance from q to the node's box; the host's
 // max(lo - q, 0, q - hi) per axis, summed in the same order.
-__host__ __device__ __forceinline__ double box_d2(const double* b, double qx, double qy, double qz)
+__host__ __device__ __forceinline__ double box_d2(const DevNode& b, double qx, double qy, double qz)
 {
-    const double dx = fmax(fmax(b[0] - qx, 0.0), qx - b[3]);
-    const double dy = fmax(fmax(b[1] - qy, 0.0), qy - b[4]);
-    const double dz = fmax(fmax(b[2] - qz, 0.0), qz - b[5]);
+    const double dx = fmax(fmax(b.lo[0] - qx, 0.0), qx - b.hi[0]);
+    const double dy = fmax(fmax(b.lo[1] - qy, 0.0), qy - b.hi[1]);
+    const double dz = fmax(fmax(b.lo[2] - qz, 0.0), qz - b.hi[2]);
     return dx * dx + dy * dy + dz * dz;
 }
 
@@ -86,19 +98,17 @@ __host__ __device__ inline int32_t check_one(const KdView& kd, double qx, double
     st[0] = 0;
     top = 1;
     while (top > 0) {
-        const int32_t node = st[--top * stride];
-        const double d2n = box_d2(kd.box + 6 * (int64_t)node, qx, qy, qz);
-        if (d2n >= best) continue;
-        const int4 lk = kd.link[node];
-        if (lk.z < 0) {
+        const DevNode nd = kd.node[st[--top * stride]];
+        if (box_d2(nd, qx, qy, qz) >= best) continue;
+        if (nd.left < 0) {
             if (budget >= 0) {
-                budget -= lk.y - lk.x;
+                budget -= nd.end - nd.begin;
                 if (budget < 0) return -2;
             }
-            for (int32_t k = lk.x; k < lk.y; ++k) {
-                const int32_t p = kd.order[k];
-                const double* pp = kd.pts + 3 * (int64_t)p;
-                const double ax = pp[0] - qx, ay = pp[1] - qy, az = pp[2] - qz;
+            for (int32_t k = nd.begin; k < nd.end; ++k) {
+                const DevLeafPt pt = kd.leaf[k];
+                const int32_t p = pt.id;
+                const double ax = pt.x - qx, ay = pt.y - qy, az = pt.z - qz;
                 const double d2 = ax * ax + ay * ay + az * az;
                 if (d2 < best || (d2 == best && bi >= 0 && p < bi)) {
                     if (excluded(excl, e0, e1, p)) continue;
@@ -108,17 +118,17 @@ __host__ __device__ inline int32_t check_one(const KdView& kd, double qx, double
             }
             continue;
         }
-        const double dl = box_d2(kd.box + 6 * (int64_t)lk.z, qx, qy, qz);
-        const double dr = box_d2(kd.box + 6 * (int64_t)lk.w, qx, qy, qz);
+        const double dl = box_d2(kd.node[nd.left], qx, qy, qz);
+        const double dr = box_d2(kd.node[nd.right], qx, qy, qz);
         // the host pushes the farther child first and takes the nearer next;
         // a pushed node is tested against the best distance when taken
         if (top + 2 > slots) return -3;
         if (dl <= dr) {
-            st[top++ * stride] = lk.w;
-            st[top++ * stride] = lk.z;
+            st[top++ * stride] = nd.right;
+            st[top++ * stride] = nd.left;
         } else {
-            st[top++ * stride] = lk.z;
-            st[top++ * stride] = lk.w;
+            st[top++ * stride] = nd.left;
+            st[top++ * stride] = nd.right;
         }
     }
     return bi;
@@ -652,16 +662,15 @@ __global__ __launch_bounds__(kBlock) void knn_kernel(KdView kd, const int32_t* _
     int cnt = 0, top = 1;
     st[0] = 0;
     while (top > 0) {
-        const int32_t node = st[--top * stride];
-        const double d2n = box_d2(kd.box + 6 * (int64_t)node, qx, qy, qz);
+        const DevNode nd = kd.node[st[--top * stride]];
+        const double d2n = box_d2(nd, qx, qy, qz);
         if (cnt == k && d2n >= bd[k - 1]) continue;
-        const int4 lk = kd.link[node];
-        if (lk.z < 0) {
-            for (int32_t j = lk.x; j < lk.y; ++j) {
-                const int32_t p = kd.order[j];
+        if (nd.left < 0) {
+            for (int32_t j = nd.begin; j < nd.end; ++j) {
+                const DevLeafPt pt = kd.leaf[j];
+                const int32_t p = pt.id;
                 if (p == s) continue;
-                const double* pp = kd.pts + 3 * (int64_t)p;
-                const double ax = pp[0] - qx, ay = pp[1] - qy, az = pp[2] - qz;
+                const double ax = pt.x - qx, ay = pt.y - qy, az = pt.z - qz;
                 const double d2 = ax * ax + ay * ay + az * az;
                 int pos;
                 if (cnt < k) {
@@ -681,18 +690,18 @@ __global__ __launch_bounds__(kBlock) void knn_kernel(KdView kd, const int32_t* _
             }
             continue;
         }
-        const double dl = box_d2(kd.box + 6 * (int64_t)lk.z, qx, qy, qz);
-        const double dr = box_d2(kd.box + 6 * (int64_t)lk.w, qx, qy, qz);
+        const double dl = box_d2(kd.node[nd.left], qx, qy, qz);
+        const double dr = box_d2(kd.node[nd.right], qx, qy, qz);
         if (top + 2 > stack_slots) {
             n_out[i] = -1;
             return;
         }
         if (dl <= dr) {
-            st[top++ * stride] = lk.w;
-            st[top++ * stride] = lk.z;
+            st[top++ * stride] = nd.right;
+            st[top++ * stride] = nd.left;
         } else {
-            st[top++ * stride] = lk.z;
-            st[top++ * stride] = lk.w;
+            st[top++ * stride] = nd.left;
+            st[top++ * stride] = nd.right;
         }
     }
     n_out[i] = cnt;
@@ -1056,16 +1065,16 @@ void upload(DevBuf& b, const T* src, size_t n)
 struct TreeCache {
     int device = -1;
     uint64_t stamp = 0;
-    void* box = nullptr;
-    void* link = nullptr;
-    void* order = nullptr;
+    void* node = nullptr;
+    void* leaf = nullptr;
     void* pts = nullptr;
+    KdView view() const { return KdView{(const DevNode*)node, (const DevLeafPt*)leaf, (const double*)pts}; }
 };
 thread_local TreeCache t_tree;
 
 void release(TreeCache& c)
 {
-    for (void* p : {c.box, c.link, c.order, c.pts})
+    for (void* p : {c.node, c.leaf, c.pts})
         if (p) (void)hipFree(p);
     c = TreeCache{};
 }
@@ -1092,12 +1101,29 @@ const TreeCache& device_tree(const KdTree& kd)
     std::vector<double> box, pts;
     std::vector<int32_t> link, order;
     kd.export_flat(box, link, order, pts);
+    const size_t nn = link.size() / 4, np = order.size();
+    std::vector<DevNode> node(nn);
+    for (size_t i = 0; i < nn; ++i) {
+        DevNode& d = node[i];
+        for (int a = 0; a < 3; ++a) {
+            d.lo[a] = box[6 * i + a];
+            d.hi[a] = box[6 * i + 3 + a];
+        }
+        d.begin = link[4 * i];
+        d.end = link[4 * i + 1];
+        d.left = link[4 * i + 2];
+        d.right = link[4 * i + 3];
+    }
+    std::vector<DevLeafPt> leaf(np);
+    for (size_t k = 0; k < np; ++k) {
+        const int32_t p = order[k];
+        leaf[k] = DevLeafPt{pts[3 * (size_t)p], pts[3 * (size_t)p + 1], pts[3 * (size_t)p + 2], p, 0};
+    }
     TreeCache c;
     c.device = dev;
     try {
-        upload_raw(c.box, box);
-        upload_raw(c.link, link);
-        upload_raw(c.order, order);
+        upload_raw(c.node, node);
+        upload_raw(c.leaf, leaf);
         upload_raw(c.pts, pts);
     } catch (...) {
         release(c);
@@ -1131,7 +1157,7 @@ void gpu_corner_checks(const CornerChecks& job, std::vector<int32_t>& out)
     upload(d_eoff, job.excl_off.data(), job.excl_off.size());
     upload(d_excl, job.excl.data(), job.excl.size());
     check(hipMalloc(&d_out.p, n * sizeof(int32_t)), "hipMalloc (corner checks)");
-    const KdView kv{(const double*)tc.box, (const int4*)tc.link, (const int32_t*)tc.order, (const double*)tc.pts};
+    const KdView kv = tc.view();
     const int64_t grid = (n + kBlock - 1) / kBlock;
     const size_t lds = (size_t)slots * kBlock * sizeof(int32_t);
     corner_check_kernel<<<(unsigned)grid, kBlock, lds>>>(kv, d_q.get<double>(), d_lim.get<double>(),
@@ -1178,7 +1204,7 @@ void cells_pass(const CellJob& job, CellResult& out)
     const int slots = kd.depth() + 1;
     if (slots > kMaxStack) throw Error(P2M_ERR_INTERNAL, "site tree too deep for the device cells");
     const TreeCache& tc = device_tree(kd);
-    const KdView kv{(const double*)tc.box, (const int4*)tc.link, (const int32_t*)tc.order, (const double*)tc.pts};
+    const KdView kv = tc.view();
 
     // one allocation, carved into the per-cell slabs and the kNN lists
     size_t total = 0;
