@@ -639,7 +639,7 @@ def main():
     kh = kernel_source_hash()
     # which search the library ran (p2m_query_config.group; 2 = automatic)
     grp = mesh.query_config()["group"]
-    grouped = grp == 1 or (grp == 2 and n >= 2000000)  # the forward's rule (fused: 8M)
+    grouped = grp == 1 or (grp == 2 and n >= 2000000)
     search_path = ("search phase of p2m_query_ordered: locate_kernel, sort by site, grouped_kernel "
                    "(list chunks shared through LDS)" if grouped else
                    "search phase of p2m_query_ordered: fwd_kernel (walk, regroup, per-lane list scans)")

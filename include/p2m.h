@@ -137,9 +137,8 @@ typedef struct {
                            site within each workgroup, per-lane list scans); 1 = three passes
                            (locate every point, sort the points by located site, then each run of
                            lanes sharing a site scans its list once, loaded 32 entries at a time
-                           through LDS); 2 (default) = the three passes for a forward of at
-                           least 2,000,000 points and a fused call of at least 8,000,000.
-                           Results are identical. */
+                           through LDS); 2 (default) = the three passes for a forward or
+                           fused call of at least 2,000,000 points.  Results are identical. */
 } p2m_query_config;
 
 void p2m_default_opts(p2m_build_opts* opts);

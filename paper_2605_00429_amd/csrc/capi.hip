@@ -209,20 +209,20 @@ struct p2m_handle_ {
 
     // Whether a non-instrumented search of n points runs as the grouped
     // passes (locate, sort by site, shared list scans): config group = 1,
-    // or automatic (2) for a forward of at least 2M points and a fused
-    // call of at least 8M.  The grouped passes cost a few hundred
-    // microseconds more in fixed work and win on large sets: forwards
-    // measured 2.59 against 3.05 ms on 10M points of the 327k-triangle
-    // mesh, 1.03 against 1.07 on its 4M near-surface points, 3.37 against
-    // 3.69 on C1's 2M, but 0.89 against 0.74 on 1M points of the same mesh
-    // and 0.57 against 0.40 on 10k; fused calls 3.59 against 3.68 ms on
-    // the 10M points but 1.43 against 1.32 on the 4M and 3.96 against
-    // 3.83 on C1.
+    // or automatic (2) for a forward or fused call of at least 2M points.
+    // The grouped passes cost a few hundred microseconds more in fixed
+    // work and win on large sets: forwards measured 2.53 against 3.03 ms
+    // on 10M points of the 327k-triangle mesh, 1.01 against 1.07 on its 4M
+    // near-surface points, 3.26 against 3.60 on C1's 2M, but 0.87 against
+    // 0.73 on 1M points of the same mesh and 0.54 against 0.38 on 10k;
+    // fused calls 2.87 against 3.61 ms on the 10M points, 1.18 against
+    // 1.30 on the 4M, 3.32 against 3.75 on C1, 0.92 against 0.85 on 1M.
     bool grouped(int64_t n, bool fused) const
     {
         if (cfg.group == 0) return false;
         if (cfg.group == 1) return true;
-        return n >= (fused ? 8000000 : 2000000);
+        (void)fused;
+        return n >= 2000000;
     }
 
     // The search of `a` (sorted or not): the grouped passes or the one-pass

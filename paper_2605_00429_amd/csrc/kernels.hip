@@ -1546,6 +1546,14 @@ inline int acc_slots_for(int block)
 
 inline size_t acc_lds_bytes(int slots) { return (size_t)slots * 16; }
 
+// Slots of a fused search's table: 256 (4 KB).  The table shares the
+// workgroup with the search, and its LDS limits how many search
+// wavefronts run at once: on C2's 10M points the grouped fused pass took
+// 3.52 ms with 1,024 slots, 3.01 with 512 and 2.89 with 256 (128 and 64
+// no better), the one-pass fused kernel 3.68 and 3.60 ms.  Contributions
+// that find no free slot go straight to global memory.
+inline int fused_acc_slots(int block) { return std::min(acc_slots_for(block), 256); }
+
 // Slots of an LDS table plus its 16-byte count within 64 KB of LDS.
 inline int acc_slots_capped(int want)
 {
@@ -1792,7 +1800,7 @@ hipError_t launch_forward(const DevMesh& m, const FwdArgs& a, int block, bool fu
     const size_t rg_bytes = 4 * (size_t)search_lds_ints(block, args.stage);
     if (fused) {
         // the table within 64 KB of LDS together with the regroup's area
-        int slots = acc_slots_for(block);
+        int slots = fused_acc_slots(block);
         while (slots > 64 && rg_bytes + acc_lds_bytes(slots) > 65536) slots >>= 1;
         args.acc_slots = slots;
         const size_t lds = rg_bytes + (a.grad_v ? acc_lds_bytes(slots) : 0);
@@ -1934,7 +1942,7 @@ hipError_t launch_grouped(const DevMesh& m, const FwdArgs& a, void* ws, bool fus
     const size_t chunk_bytes = (size_t)nw * 64 * sizeof(ChunkEntry);
     size_t lds = chunk_bytes;
     if (fused && a.grad_v) {
-        int slots = acc_slots_for(block);
+        int slots = fused_acc_slots(block);
         while (slots > 64 && chunk_bytes + acc_lds_bytes(slots) > 65536) slots >>= 1;
         args.acc_slots = slots;
         lds += acc_lds_bytes(slots);
@@ -2016,7 +2024,7 @@ hipError_t launch_batch(const DevMesh* meshes, const BatchArgs& a, int grid, int
     args.stage = stage > 0 ? std::min(kStageEntries, 49152 / (16 * (block / 64))) : 0;
     const size_t rg_bytes = 4 * (size_t)search_lds_ints(block, args.stage);
     if (fused) {
-        int slots = acc_slots_for(block);
+        int slots = fused_acc_slots(block);
         while (slots > 64 && rg_bytes + acc_lds_bytes(slots) > 65536) slots >>= 1;
         args.acc_slots = slots;
         const size_t lds = rg_bytes + (a.grad_v ? acc_lds_bytes(slots) : 0);
