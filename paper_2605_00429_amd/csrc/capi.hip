@@ -217,11 +217,10 @@ struct p2m_handle_ {
     // 0.73 on 1M points of the same mesh and 0.54 against 0.38 on 10k;
     // fused calls 2.87 against 3.61 ms on the 10M points, 1.18 against
     // 1.30 on the 4M, 3.32 against 3.75 on C1, 0.92 against 0.85 on 1M.
-    bool grouped(int64_t n, bool fused) const
+    bool grouped(int64_t n) const
     {
         if (cfg.group == 0) return false;
         if (cfg.group == 1) return true;
-        (void)fused;
         return n >= 2000000;
     }
 
@@ -229,7 +228,7 @@ struct p2m_handle_ {
     // kernel.  The caller holds mu.
     int32_t search(const p2m::FwdArgs& a, bool fused, hipStream_t st)
     {
-        if (grouped(a.n, fused)) {
+        if (grouped(a.n)) {
             void* gw = nullptr;
             const int32_t rc = ensure_gws(p2m::grouped_workspace_bytes(a.n, dm.n_sites), st, &gw);
             if (rc != P2M_OK) return rc;
