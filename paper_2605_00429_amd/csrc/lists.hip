@@ -120,24 +120,28 @@ constexpr int kWaves = 4;  // wavefronts (sites) per workgroup
 // lane's live ball passes the triangle-box prefilter and the exact distance
 // test.  The node and triangle loads are the same for the whole wavefront.
 // The set of triangles is the host's (its order, which the layout stage
-// re-sorts, is not).  Pass 1 (kFill = false) counts, pass 2 writes the
-// triangle ids from off[site].  A traversal that would overflow its stack
-// (never for a BVH of at most 2^29 triangles) reports count -1, and the
-// host builds that list itself.
+// re-sorts, is not).  Pass 1 (kFill = false) counts, and keeps the first
+// kRowCap ids of each list in that site's row of `rows`; pass 2 writes the
+// ids from off[site] again, for the lists longer than a row only (the
+// others are copied from their rows).  A traversal that would overflow its
+// stack (never for a BVH of at most 2^29 triangles) reports count -1, and
+// the host builds that list itself.
 static_assert(64 * kLaneBalls >= kDeviceBalls, "a wavefront must hold every ball the host sends");
+constexpr int kRowCap = 256;
 
 template <bool kFill>
 __global__ void __launch_bounds__(64 * kWaves)
 list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, const double* __restrict__ T,
             const int64_t* __restrict__ ball_off, const double* __restrict__ balls, int64_t n_sites,
-            int64_t* __restrict__ counts, const int64_t* __restrict__ off, int32_t* __restrict__ ids)
+            int64_t* __restrict__ counts, const int64_t* __restrict__ off, int32_t* __restrict__ ids,
+            int32_t* __restrict__ rows)
 {
     __shared__ int32_t s_node[kWaves][kStack];
     __shared__ uint8_t s_mask[kWaves][kStack][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t si = (int64_t)blockIdx.x * kWaves + wv;
     if (si >= n_sites) return;  // the whole wavefront
-    if (kFill && counts[si] < 0) return;
+    if (kFill && (counts[si] < 0 || counts[si] <= kRowCap)) return;
     const int64_t b0 = ball_off[si];
     const int nb = (int)(ball_off[si + 1] - b0);
     double bx[kLaneBalls], by[kLaneBalls], bz[kLaneBalls], r2[kLaneBalls];
@@ -197,6 +201,7 @@ list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, 
                 }
                 if (__ballot(hit) != 0) {
                     if (kFill && lane == 0) ids[w] = t;
+                    if (!kFill && lane == 0 && cnt < kRowCap) rows[si * kRowCap + cnt] = t;
                     ++w;
                     ++cnt;
                 }
@@ -215,6 +220,19 @@ list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, 
         ++sp;
     }
     if (!kFill && lane == 0) counts[si] = overflow ? -1 : cnt;
+}
+
+// Lists that fit their row: copied to their place in the packed array.
+__global__ void __launch_bounds__(64 * kWaves)
+copy_rows_kernel(const int32_t* __restrict__ rows, const int64_t* __restrict__ counts,
+                 const int64_t* __restrict__ off, int64_t n_sites, int32_t* __restrict__ ids)
+{
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t si = (int64_t)blockIdx.x * kWaves + wv;
+    if (si >= n_sites) return;
+    const int64_t c = counts[si];
+    if (c < 0 || c > kRowCap) return;
+    for (int64_t k = lane; k < c; k += 64) ids[off[si] + k] = rows[si * kRowCap + k];
 }
 
 struct DevBuf {
@@ -272,11 +290,13 @@ void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vect
     upload(d_boff, job.ball_off.data(), job.ball_off.size());
     upload(d_balls, job.balls.data(), job.balls.size());
     check(hipMalloc(&d_counts.p, ns * sizeof(int64_t)), "hipMalloc (list build)");
+    DevBuf d_rows;
+    check(hipMalloc(&d_rows.p, (size_t)ns * kRowCap * sizeof(int32_t)), "hipMalloc (list build)");
     const int block = 64 * kWaves;
     const int grid = (int)((ns + kWaves - 1) / kWaves);
     list_kernel<false><<<grid, block>>>(d_nodes.get<GNode>(), d_order.get<int32_t>(), d_T.get<double>(),
                                         d_boff.get<int64_t>(), d_balls.get<double>(), ns, d_counts.get<int64_t>(),
-                                        nullptr, nullptr);
+                                        nullptr, nullptr, d_rows.get<int32_t>());
     check(hipGetLastError(), "list count launch");
     std::vector<int64_t> counts(ns);
     check(hipMemcpy(counts.data(), d_counts.p, ns * sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy (counts)");
@@ -284,10 +304,18 @@ void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vect
     const int64_t total = off[ns];
     upload(d_off, off.data(), off.size());
     check(hipMalloc(&d_ids.p, total ? total * sizeof(int32_t) : 16), "hipMalloc (list build)");
-    list_kernel<true><<<grid, block>>>(d_nodes.get<GNode>(), d_order.get<int32_t>(), d_T.get<double>(),
-                                       d_boff.get<int64_t>(), d_balls.get<double>(), ns, d_counts.get<int64_t>(),
-                                       d_off.get<int64_t>(), d_ids.get<int32_t>());
-    check(hipGetLastError(), "list fill launch");
+    copy_rows_kernel<<<grid, block>>>(d_rows.get<int32_t>(), d_counts.get<int64_t>(), d_off.get<int64_t>(), ns,
+                                      d_ids.get<int32_t>());
+    check(hipGetLastError(), "list copy launch");
+    bool longer = false;
+    for (int64_t i = 0; i < ns && !longer; ++i) longer = counts[i] > kRowCap;
+    if (longer) {
+        list_kernel<true><<<grid, block>>>(d_nodes.get<GNode>(), d_order.get<int32_t>(), d_T.get<double>(),
+                                           d_boff.get<int64_t>(), d_balls.get<double>(), ns,
+                                           d_counts.get<int64_t>(), d_off.get<int64_t>(), d_ids.get<int32_t>(),
+                                           nullptr);
+        check(hipGetLastError(), "list fill launch");
+    }
     ids.resize(total);
     if (total)
         check(hipMemcpy(ids.data(), d_ids.p, total * sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy (lists)");
