@@ -143,6 +143,8 @@ constexpr double kCornerSlack = 1e-6;
 // Sites whose cells are in progress at once (bounds the memory of the
 // clipped polytopes kept between check rounds).
 constexpr int64_t kCellChunk = 32768;
+// Sites whose cells one device call builds.
+constexpr int64_t kDeviceCellChunk = int64_t(1) << 20;
 
 // One cell under construction: the clipped polytope, the sites tried so far
 // (sorted; the exclusion list of its checks), the corners found final, and
@@ -314,8 +316,11 @@ void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, 
     std::vector<CellScratch> scr(nth);
     const int64_t n = (int64_t)sites.size();
     if (kd.depth() + 1 > KdTree::kBelowStack) throw Error(P2M_ERR_INTERNAL, "site tree too deep");
-    for (int64_t c0 = 0; c0 < n; c0 += kCellChunk) {
-        const int64_t m = std::min(kCellChunk, n - c0);
+    // the device keeps its cells in its own memory, so its chunks are
+    // larger (the host keeps only their corners and face sites)
+    const int64_t step = cells ? kDeviceCellChunk : kCellChunk;
+    for (int64_t c0 = 0; c0 < n; c0 += step) {
+        const int64_t m = std::min(step, n - c0);
         if (cells) {
             CellJob job;
             job.kd = &kd;

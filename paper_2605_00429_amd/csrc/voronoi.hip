@@ -1179,13 +1179,30 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 namespace {
 
-// Cells per device pass: each holds a 118 KB slab, so a pass needs at most
-// about 3.9 GB of device memory.  (Passes of 16,384 cells took the C2
-// mesh's Voronoi stage from 0.70 to 0.88 s: each pass's last rounds have
-// few cells left in progress.)
-constexpr int64_t kDevCells = 32768;
+// Device memory of one cell in a pass (its slab and its kNN list).
+size_t cell_bytes(int knn)
+{
+    return sizeof(CellHdr) + sizeof(DFace) * 2 * kFCap + sizeof(double) * 2 * 3 * kVCap +
+           sizeof(double) * 3 * kCutCap + sizeof(int32_t) * kTCap + sizeof(double) * 3 * kQCap +
+           sizeof(double) * 3 * kVCap + sizeof(int32_t) * kFCap + sizeof(int32_t) * 5 + sizeof(int64_t) * 2 +
+           (sizeof(double) + sizeof(int32_t)) * (size_t)knn;
+}
 
-// gpu_cells for one pass of at most kDevCells cells.
+// Cells per device pass: as many as a quarter of the free device memory
+// holds (at most 32 GiB), and at least 32,768.  Every pass ends with rounds
+// that only its slowest checks fill (each round lasts as long as its
+// slowest check), so fewer, larger passes finish sooner: passes of 16,384
+// cells took the C2 mesh's Voronoi stage from 0.70 to 0.88 s.
+int64_t pass_cells(int64_t n, int knn)
+{
+    size_t free_b = 0, total_b = 0;
+    check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    const size_t budget = std::min(free_b / 4, (size_t)32 << 30);
+    const int64_t cap = std::max<int64_t>(32768, (int64_t)(budget / cell_bytes(knn)));
+    return std::min(n, cap);
+}
+
+// gpu_cells for one pass.
 void cells_pass(const CellJob& job, CellResult& out)
 {
     const int64_t m = job.n;
@@ -1333,7 +1350,8 @@ void cells_pass(const CellJob& job, CellResult& out)
 
 void gpu_cells(const CellJob& job, CellResult& out)
 {
-    if (job.n <= kDevCells) {
+    const int64_t per = job.n > 0 ? pass_cells(job.n, job.knn) : 1;
+    if (job.n <= per) {
         cells_pass(job, out);
         return;
     }
@@ -1344,10 +1362,10 @@ void gpu_cells(const CellJob& job, CellResult& out)
     out.ok.clear();
     out.unresolved.clear();
     out.redo.clear();
-    for (int64_t c0 = 0; c0 < job.n; c0 += kDevCells) {
+    for (int64_t c0 = 0; c0 < job.n; c0 += per) {
         CellJob part = job;
         part.sites = job.sites + c0;
-        part.n = std::min(kDevCells, job.n - c0);
+        part.n = std::min(per, job.n - c0);
         CellResult r;
         cells_pass(part, r);
         const int64_t cb = out.corner_off.back(), fb = out.face_off.back();
