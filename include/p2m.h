@@ -103,6 +103,11 @@ typedef struct {
                                   three (needs device >= 0 for 1 and 2) */
     int32_t device;            /* HIP device to upload to; -2 (default) = the current
                                   device; -1 = host only (inspection, no query calls) */
+    int32_t gpu_cell_pass;     /* with gpu_voronoi = 1: cells built per device pass, each
+                                  taking about 118 KB of device memory during the build;
+                                  0 (default) = as many as a quarter of the free device
+                                  memory holds, at most 32 GiB of them.  The cells are the
+                                  same for any value (>= 0) */
 } p2m_build_opts;
 
 /* Statistics of a built handle (list lengths as in Table 1 of the paper). */

@@ -39,7 +39,7 @@ class p2m_build_opts(ctypes.Structure):
                 ("n_threads", ctypes.c_int32), ("decomposition", ctypes.c_int32),
                 ("octree_max_list", ctypes.c_int32), ("octree_max_depth", ctypes.c_int32),
                 ("gpu_lists", ctypes.c_int32), ("gpu_voronoi", ctypes.c_int32),
-                ("device", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("gpu_cell_pass", ctypes.c_int32)]
 
 
 class p2m_stats(ctypes.Structure):

@@ -271,6 +271,7 @@ void p2m_default_opts(p2m_build_opts* o)
     o->aux_list_mode = 1;
     o->gpu_lists = 1;
     o->gpu_voronoi = 1;
+    o->gpu_cell_pass = 0;
     o->decomposition = 0;
     o->octree_max_list = 64;
     o->octree_max_depth = 12;

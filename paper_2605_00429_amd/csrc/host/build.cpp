@@ -310,7 +310,7 @@ void cell_done(CellState& c, int64_t i, int tid, CellScratch& w, const CellDone&
 // tid, corners, faces, ok, unresolved) receives sites[i]'s cell inside a
 // parallel loop.
 void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, const KdTree& kd, d3 blo, d3 bhi,
-                   int64_t budget, int nth, const CheckFn& check, bool host_tail, const CellFn* cells,
+                   int64_t budget, int nth, const CheckFn& check, bool host_tail, const CellFn* cells, int64_t pass,
                    p2m_stats& stats, const CellDone& done)
 {
     std::vector<CellScratch> scr(nth);
@@ -332,6 +332,7 @@ void compute_cells(const std::vector<int32_t>& sites, const std::vector<d3>& P, 
             job.max_faces = kPass1MaxFaces;
             job.knn = kKnn;
             job.slack = kCornerSlack;
+            job.pass = pass;
             CellResult r;
             (*cells)(job, r);
             const int64_t n_redo = std::count(r.redo.begin(), r.redo.end(), (char)1);
@@ -536,7 +537,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     if (!(o.domain_scale >= 1.0f) || !(o.tau_scale > 0) || o.ring_sites < 0 || o.ring_layers < 0 ||
         !(o.list_inflation_rel >= 0) || !(o.seed_cell_scale > 0) || o.seed_max_cells < 1 ||
         o.decomposition < 0 || o.decomposition > 1 || o.octree_max_list < 1 || o.octree_max_depth < 0 ||
-        o.octree_max_depth > 16 || o.gpu_voronoi < 0 || o.gpu_voronoi > 2)
+        o.octree_max_depth > 16 || o.gpu_voronoi < 0 || o.gpu_voronoi > 2 || o.gpu_cell_pass < 0)
         throw Error(P2M_ERR_INVALID_ARG, "invalid build option");
     const int nth = resolve_threads(o.n_threads);
     const int64_t nV = mesh.n_vertices, nT = mesh.n_triangles;
@@ -676,7 +677,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         std::vector<std::vector<std::pair<uint64_t, d3>>> site_keys(nVS);
         std::vector<int32_t> vsites(nVS);
         std::iota(vsites.begin(), vsites.end(), 0);
-        compute_cells(vsites, P, kd, blo, bhi, kPass1Budget, nth, checks, gpu_checks != nullptr, gpu_cells, H.stats,
+        compute_cells(vsites, P, kd, blo, bhi, kPass1Budget, nth, checks, gpu_checks != nullptr, gpu_cells, o.gpu_cell_pass, H.stats,
                       [&](int64_t s, int, const std::vector<d3>& corners, const std::vector<int32_t>& faces, bool ok,
                           bool unres) {
             cell_corners[s] = corners;
@@ -865,7 +866,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
                 std::vector<int32_t> asites;
                 for (size_t i = 0; i < aux.size(); ++i)
                     if (need[i]) asites.push_back(nVS + (int32_t)i);
-                compute_cells(asites, PP, kd2, blo, bhi, -1, nth, checks, gpu_checks != nullptr, gpu_cells, H.stats,
+                compute_cells(asites, PP, kd2, blo, bhi, -1, nth, checks, gpu_checks != nullptr, gpu_cells, o.gpu_cell_pass, H.stats,
                               [&](int64_t j, int, const std::vector<d3>&, const std::vector<int32_t>& faces, bool ok,
                                   bool) {
                     const int32_t i = asites[j] - nVS;
@@ -939,7 +940,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         std::vector<int32_t> todo;
         for (int32_t s = 0; s < nS; ++s)
             if (!cell_done[s]) todo.push_back(s);
-        compute_cells(todo, P, kd, blo, bhi, -1, nth, checks, gpu_checks != nullptr, gpu_cells, H.stats,
+        compute_cells(todo, P, kd, blo, bhi, -1, nth, checks, gpu_checks != nullptr, gpu_cells, o.gpu_cell_pass, H.stats,
                       [&](int64_t i, int, const std::vector<d3>& corners, const std::vector<int32_t>& faces, bool ok,
                           bool) {
             const int32_t s = todo[i];

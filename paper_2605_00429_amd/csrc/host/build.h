@@ -121,6 +121,7 @@ struct CellJob {
     int32_t max_faces = 0;
     int32_t knn = 0;
     double slack = 0;
+    int64_t pass = 0;  // cells per device pass; 0 = as device memory allows
 };
 // Per cell i: its distinct corners relative to the site (sorted as
 // ClipCell::corners gives them) in corners[corner_off[i] .. corner_off[i+1]),

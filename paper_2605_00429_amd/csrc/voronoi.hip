@@ -1350,7 +1350,7 @@ void cells_pass(const CellJob& job, CellResult& out)
 
 void gpu_cells(const CellJob& job, CellResult& out)
 {
-    const int64_t per = job.n > 0 ? pass_cells(job.n, job.knn) : 1;
+    const int64_t per = job.pass > 0 ? std::min(job.n, job.pass) : (job.n > 0 ? pass_cells(job.n, job.knn) : 1);
     if (job.n <= per) {
         cells_pass(job, out);
         return;

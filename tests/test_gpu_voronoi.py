@@ -102,6 +102,18 @@ def test_device_cells_hand_large_cells_back(dev):
     assert st["n_cells_host"] > 0 and st["n_cells_device"] > 0, st
 
 
+def test_device_cells_in_small_passes(dev):
+    """gpu_cell_pass splits the device cells into passes (here of 1,000 and
+    of 777 cells, so that the last pass is ragged): the structure is still
+    the host's, with and without cells handed back to the host."""
+    for name, (V, F) in (("icosphere-5", gen.icosphere(5)), ("cylinder 256x16", gen.cylinder_cone(256, 16))):
+        m0 = dev.Mesh(V, F, gpu_voronoi=0)
+        for per in (1000, 777):
+            m = dev.Mesh(V, F, gpu_voronoi=1, gpu_cell_pass=per)
+            assert_same_structure(m0, m, f"{name} passes of {per}")
+            assert m.stats()["n_cells_device"] > 0
+
+
 def test_device_cells_full_size(dev):
     """The displaced icosphere-7 (327,680 triangles): identical statistics
     and site positions, 3,000 sampled sites' neighbours and lists, in each

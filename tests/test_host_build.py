@@ -182,7 +182,8 @@ def test_unreferenced_duplicate_and_degenerate_input():
     check_exact(m, V2, F2, Q)
 
 
-@pytest.mark.parametrize("case", ["no_tris", "bad_index", "neg_index", "nan_vertex", "bad_opt", "bad_voronoi_mode"])
+@pytest.mark.parametrize("case", ["no_tris", "bad_index", "neg_index", "nan_vertex", "bad_opt", "bad_voronoi_mode",
+                                  "bad_cell_pass"])
 def test_build_errors(case):
     V, F = gen.tetrahedron()
     kw = {}
@@ -200,6 +201,9 @@ def test_build_errors(case):
         code = p2m._lib.P2M_ERR_BAD_MESH
     elif case == "bad_voronoi_mode":
         kw = dict(gpu_voronoi=3)
+        code = p2m._lib.P2M_ERR_INVALID_ARG
+    elif case == "bad_cell_pass":
+        kw = dict(gpu_cell_pass=-1)
         code = p2m._lib.P2M_ERR_INVALID_ARG
     else:
         kw = dict(domain_scale=0.5)
