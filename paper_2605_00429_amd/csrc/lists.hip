@@ -129,28 +129,46 @@ constexpr int kWaves = 4;  // wavefronts (sites) per workgroup
 static_assert(64 * kLaneBalls >= kDeviceBalls, "a wavefront must hold every ball the host sends");
 constexpr int kRowCap = 256;
 
-template <bool kFill>
+// kSub lanes per site (64, 32 or 16: sites with at most kSub * kLB balls
+// share a wavefront, each group of lanes walking the BVH with its own
+// stack; a group's steps stay uniform, and the wavefront runs until every
+// group is done).  Sites are taken from sel (indices into the job's
+// sites).
+template <bool kFill, int kSub, int kLB>
 __global__ void __launch_bounds__(64 * kWaves)
 list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, const double* __restrict__ T,
-            const int64_t* __restrict__ ball_off, const double* __restrict__ balls, int64_t n_sites,
-            int64_t* __restrict__ counts, const int64_t* __restrict__ off, int32_t* __restrict__ ids,
-            int32_t* __restrict__ rows)
+            const int64_t* __restrict__ ball_off, const double* __restrict__ balls,
+            const int32_t* __restrict__ sel, int64_t n_sel, int64_t* __restrict__ counts,
+            const int64_t* __restrict__ off, int32_t* __restrict__ ids, int32_t* __restrict__ rows)
 {
-    __shared__ int32_t s_node[kWaves][kStack];
-    __shared__ uint8_t s_mask[kWaves][kStack][64];
+    static_assert(kSub == 64 || kSub == 32 || kSub == 16, "groups of 64, 32 or 16 lanes");
+    constexpr int kPer = 64 / kSub;
+    __shared__ int32_t s_node[kWaves][kPer][kStack];
+    __shared__ uint8_t s_mask[kWaves][kPer][kStack][kSub];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t si = (int64_t)blockIdx.x * kWaves + wv;
-    if (si >= n_sites) return;  // the whole wavefront
-    if (kFill && (counts[si] < 0 || counts[si] <= kRowCap)) return;
-    const int64_t b0 = ball_off[si];
-    const int nb = (int)(ball_off[si + 1] - b0);
-    double bx[kLaneBalls], by[kLaneBalls], bz[kLaneBalls], r2[kLaneBalls];
+    const int sub = lane / kSub, sl = lane % kSub;
+    const uint64_t group = kSub == 64 ? ~0ull : (((1ull << kSub) - 1) << (sub * kSub));
+    const int64_t k_sel = ((int64_t)blockIdx.x * kWaves + wv) * kPer + sub;
+    int64_t si = -1;  // this group's site, or none
+    if (k_sel < n_sel) {
+        si = sel[k_sel];
+        // the second walk only for lists longer than a row
+        if (kFill && (counts[si] < 0 || counts[si] <= kRowCap)) si = -1;
+    }
+    if (__ballot(si >= 0) == 0) return;  // the whole wavefront
+    int nb = 0;
+    int64_t b0 = 0;
+    if (si >= 0) {
+        b0 = ball_off[si];
+        nb = (int)(ball_off[si + 1] - b0);
+    }
+    double bx[kLB], by[kLB], bz[kLB], r2[kLB];
     unsigned live = 0;
 #pragma unroll
-    for (int j = 0; j < kLaneBalls; ++j) {
-        const int k = lane + 64 * j;
+    for (int j = 0; j < kLB; ++j) {
+        const int k = sl + kSub * j;
         bx[j] = by[j] = bz[j] = r2[j] = 0.0;
-        if (k < nb) {
+        if (si >= 0 && k < nb) {
             const double* B = balls + 4 * (b0 + k);
             bx[j] = B[0];
             by[j] = B[1];
@@ -160,28 +178,32 @@ list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, 
         }
     }
     int64_t cnt = 0;
-    int64_t w = kFill ? off[si] : 0;
+    int64_t w = (kFill && si >= 0) ? off[si] : 0;
     int sp = 0;
-    // every lane writes the same node id, and reads back what it wrote
-    s_node[wv][sp] = 0;
-    s_mask[wv][sp][lane] = (uint8_t)live;
-    ++sp;
+    if (si >= 0) {
+        // every lane of the group writes the same node id, and reads back what it wrote
+        s_node[wv][sub][0] = 0;
+        s_mask[wv][sub][0][sl] = (uint8_t)live;
+        sp = 1;
+    }
     bool overflow = false;
-    while (sp > 0) {
+    while (__ballot(sp > 0) != 0) {
+        if (sp == 0) continue;
         --sp;
-        const int32_t node = __builtin_amdgcn_readfirstlane(s_node[wv][sp]);
-        const unsigned lm = s_mask[wv][sp][lane];
+        // one group per wavefront: the node is the same in every lane
+        const int32_t node = kSub == 64 ? __builtin_amdgcn_readfirstlane(s_node[wv][sub][sp]) : s_node[wv][sub][sp];
+        const unsigned lm = s_mask[wv][sub][sp][sl];
         const GNode n = nodes[node];
         unsigned m = 0;
 #pragma unroll
-        for (int j = 0; j < kLaneBalls; ++j) {
+        for (int j = 0; j < kLB; ++j) {
             if (!((lm >> j) & 1u)) continue;
             const double dx = gmax3(n.lo[0] - bx[j], 0.0, bx[j] - n.hi[0]);
             const double dy = gmax3(n.lo[1] - by[j], 0.0, by[j] - n.hi[1]);
             const double dz = gmax3(n.lo[2] - bz[j], 0.0, bz[j] - n.hi[2]);
             if (dx * dx + dy * dy + dz * dz <= r2[j]) m |= 1u << j;
         }
-        if (__ballot(m != 0) == 0) continue;
+        if ((__ballot(m != 0) & group) == 0) continue;
         if (n.b < 0) {
             for (int32_t i = n.a; i < n.a - n.b; ++i) {
                 const int32_t t = order[i];
@@ -191,7 +213,7 @@ list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, 
                 const G3 hi{fmax(a.x, fmax(b.x, c.x)), fmax(a.y, fmax(b.y, c.y)), fmax(a.z, fmax(b.z, c.z))};
                 bool hit = false;
 #pragma unroll
-                for (int j = 0; j < kLaneBalls; ++j) {
+                for (int j = 0; j < kLB; ++j) {
                     if (hit || !((m >> j) & 1u)) continue;
                     const double dx = gmax3(lo.x - bx[j], 0.0, bx[j] - hi.x);
                     const double dy = gmax3(lo.y - by[j], 0.0, by[j] - hi.y);
@@ -199,9 +221,9 @@ list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, 
                     if (dx * dx + dy * dy + dz * dz > r2[j]) continue;
                     hit = tri_dist2(G3{bx[j], by[j], bz[j]}, a, b, c) <= r2[j];
                 }
-                if (__ballot(hit) != 0) {
-                    if (kFill && lane == 0) ids[w] = t;
-                    if (!kFill && lane == 0 && cnt < kRowCap) rows[si * kRowCap + cnt] = t;
+                if ((__ballot(hit) & group) != 0) {
+                    if (kFill && sl == 0) ids[w] = t;
+                    if (!kFill && sl == 0 && cnt < kRowCap) rows[si * kRowCap + cnt] = t;
                     ++w;
                     ++cnt;
                 }
@@ -210,16 +232,17 @@ list_kernel(const GNode* __restrict__ nodes, const int32_t* __restrict__ order, 
         }
         if (sp + 2 > kStack) {
             overflow = true;
-            break;
+            sp = 0;
+            continue;
         }
-        s_node[wv][sp] = n.b;
-        s_mask[wv][sp][lane] = (uint8_t)m;
+        s_node[wv][sub][sp] = n.b;
+        s_mask[wv][sub][sp][sl] = (uint8_t)m;
         ++sp;
-        s_node[wv][sp] = node + 1;
-        s_mask[wv][sp][lane] = (uint8_t)m;
+        s_node[wv][sub][sp] = node + 1;
+        s_mask[wv][sub][sp][sl] = (uint8_t)m;
         ++sp;
     }
-    if (!kFill && lane == 0) counts[si] = overflow ? -1 : cnt;
+    if (!kFill && si >= 0 && sl == 0) counts[si] = overflow ? -1 : cnt;
 }
 
 // Lists that fit their row: copied to their place in the packed array.
@@ -294,9 +317,37 @@ void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vect
     check(hipMalloc(&d_rows.p, (size_t)ns * kRowCap * sizeof(int32_t)), "hipMalloc (list build)");
     const int block = 64 * kWaves;
     const int grid = (int)((ns + kWaves - 1) / kWaves);
-    list_kernel<false><<<grid, block>>>(d_nodes.get<GNode>(), d_order.get<int32_t>(), d_T.get<double>(),
-                                        d_boff.get<int64_t>(), d_balls.get<double>(), ns, d_counts.get<int64_t>(),
-                                        nullptr, nullptr, d_rows.get<int32_t>());
+    // sites by ball count: up to 16 and up to 32 balls share a wavefront
+    std::vector<int32_t> sel[3];
+    for (int64_t i = 0; i < ns; ++i) {
+        const int64_t nb = job.ball_off[i + 1] - job.ball_off[i];
+        sel[nb <= 16 ? 0 : (nb <= 32 ? 1 : 2)].push_back((int32_t)i);
+    }
+    DevBuf d_sel[3];
+    for (int c = 0; c < 3; ++c) upload(d_sel[c], sel[c].data(), sel[c].size());
+    auto launch = [&](bool fill) {
+        const GNode* nd = d_nodes.get<GNode>();
+        const int32_t* od = d_order.get<int32_t>();
+        const double* Td = d_T.get<double>();
+        const int64_t* bo = d_boff.get<int64_t>();
+        const double* bl = d_balls.get<double>();
+        int64_t* cn = d_counts.get<int64_t>();
+        const int64_t* of = fill ? d_off.get<int64_t>() : nullptr;
+        int32_t* id = fill ? d_ids.get<int32_t>() : nullptr;
+        int32_t* rw = fill ? nullptr : d_rows.get<int32_t>();
+        const int64_t n16 = (int64_t)sel[0].size(), n32 = (int64_t)sel[1].size(), n64 = (int64_t)sel[2].size();
+        auto g = [](int64_t n, int per) { return (unsigned)((n + kWaves * per - 1) / (kWaves * per)); };
+        if (fill) {
+            if (n16) list_kernel<true, 16, 1><<<g(n16, 4), block>>>(nd, od, Td, bo, bl, d_sel[0].get<int32_t>(), n16, cn, of, id, rw);
+            if (n32) list_kernel<true, 32, 1><<<g(n32, 2), block>>>(nd, od, Td, bo, bl, d_sel[1].get<int32_t>(), n32, cn, of, id, rw);
+            if (n64) list_kernel<true, 64, kLaneBalls><<<g(n64, 1), block>>>(nd, od, Td, bo, bl, d_sel[2].get<int32_t>(), n64, cn, of, id, rw);
+        } else {
+            if (n16) list_kernel<false, 16, 1><<<g(n16, 4), block>>>(nd, od, Td, bo, bl, d_sel[0].get<int32_t>(), n16, cn, of, id, rw);
+            if (n32) list_kernel<false, 32, 1><<<g(n32, 2), block>>>(nd, od, Td, bo, bl, d_sel[1].get<int32_t>(), n32, cn, of, id, rw);
+            if (n64) list_kernel<false, 64, kLaneBalls><<<g(n64, 1), block>>>(nd, od, Td, bo, bl, d_sel[2].get<int32_t>(), n64, cn, of, id, rw);
+        }
+    };
+    launch(false);
     check(hipGetLastError(), "list count launch");
     std::vector<int64_t> counts(ns);
     check(hipMemcpy(counts.data(), d_counts.p, ns * sizeof(int64_t), hipMemcpyDeviceToHost), "hipMemcpy (counts)");
@@ -310,10 +361,7 @@ void gpu_build_lists(const GpuListJob& job, std::vector<int64_t>& off, std::vect
     bool longer = false;
     for (int64_t i = 0; i < ns && !longer; ++i) longer = counts[i] > kRowCap;
     if (longer) {
-        list_kernel<true><<<grid, block>>>(d_nodes.get<GNode>(), d_order.get<int32_t>(), d_T.get<double>(),
-                                           d_boff.get<int64_t>(), d_balls.get<double>(), ns,
-                                           d_counts.get<int64_t>(), d_off.get<int64_t>(), d_ids.get<int32_t>(),
-                                           nullptr);
+        launch(true);
         check(hipGetLastError(), "list fill launch");
     }
     ids.resize(total);
