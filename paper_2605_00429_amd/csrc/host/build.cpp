@@ -1043,7 +1043,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     for (int64_t i = 0; i < nT; ++i) slot_of[torder[i]] = (int32_t)i;
     // bounding spheres (user order)
     std::vector<float> sph(4 * nT);
-    for (int64_t t = 0; t < nT; ++t) {
+    parallel_for(nT, nth, [&](int64_t t, int) {
         const d3 a = T[3 * t], b = T[3 * t + 1], c = T[3 * t + 2];
         const d3 cc = min_sphere_center(a, b, c);
         const float cx = (float)cc.x, cy = (float)cc.y, cz = (float)cc.z;
@@ -1053,7 +1053,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         sph[4 * t + 1] = cy;
         sph[4 * t + 2] = cz;
         sph[4 * t + 3] = round_up(r * (1.0 + 1e-6));
-    }
+    }, 4096);
     // site order: Morton code of position
     std::vector<int32_t> sorder(nS);
     std::iota(sorder.begin(), sorder.end(), 0);
@@ -1061,7 +1061,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         const double ext = std::max({mhi.x - mlo.x, mhi.y - mlo.y, mhi.z - mlo.z, 1e-30});
         const double inv = 2097151.0 / ext;
         std::vector<uint64_t> key(nS);
-        for (int32_t s = 0; s < nS; ++s) key[s] = morton_of(P[s], mlo, inv);
+        parallel_for(nS, nth, [&](int64_t s, int) { key[s] = morton_of(P[s], mlo, inv); }, 4096);
         std::stable_sort(sorder.begin(), sorder.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
     }
     std::vector<int32_t> new_id(nS);
@@ -1071,7 +1071,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     H.tri_rec.resize(12 * (size_t)nT);
     H.tri_user.resize(nT);
     H.tri_vid.resize(4 * (size_t)nT);
-    for (int64_t i = 0; i < nT; ++i) {
+    parallel_for(nT, nth, [&](int64_t i, int) {
         const int32_t t = torder[i];
         const d3 a = T[3 * t], b = T[3 * t + 1], c = T[3 * t + 2];
         const float e1x = (float)(b.x - a.x), e1y = (float)(b.y - a.y), e1z = (float)(b.z - a.z);
@@ -1088,7 +1088,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         H.tri_vid[4 * (size_t)t + 1] = mesh.triangles[3 * t + 1];
         H.tri_vid[4 * (size_t)t + 2] = mesh.triangles[3 * t + 2];
         H.tri_vid[4 * (size_t)t + 3] = 0;
-    }
+    }, 4096);
     H.n_sites = nS;
     H.n_aux = nS - n_vertex_sites;
     H.site_rec.assign(nS, SiteRec{});
@@ -1110,7 +1110,10 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         adj_off[i + 1] = adj_off[i] + (int64_t)nbr[s].size();
         list_off[i + 1] = list_off[i] + (int64_t)lists[s].size();
     }
-    parallel_for(nS, nth, [&](int64_t i, int) {
+    // per-thread scratch for the neighbours and the list entries of a site
+    std::vector<std::vector<int32_t>> nb_scr(nth);
+    std::vector<std::vector<std::pair<float, int32_t>>> ent_scr(nth);
+    parallel_for(nS, nth, [&](int64_t i, int tid) {
         const int32_t s = sorder[i];
         const float sx = (float)P[s].x, sy = (float)P[s].y, sz = (float)P[s].z;
         SiteRec& sr = H.site_rec[i];
@@ -1123,7 +1126,8 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         sr.list_begin = (int32_t)list_off[i];
         sr.list_end = (int32_t)list_off[i + 1];
         H.site_is_aux[i] = is_aux[s];
-        std::vector<int32_t> nb(nbr[s].size());
+        std::vector<int32_t>& nb = nb_scr[tid];
+        nb.resize(nbr[s].size());
         for (size_t k = 0; k < nb.size(); ++k) nb[k] = new_id[nbr[s][k]];
         std::sort(nb.begin(), nb.end());
         for (size_t k = 0; k < nb.size(); ++k) {
@@ -1136,7 +1140,8 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         }
         // list entries sorted by ell = |s - c| - r (rounded down)
         const d3 sf{sx, sy, sz};
-        std::vector<std::pair<float, int32_t>> ent(lists[s].size());
+        std::vector<std::pair<float, int32_t>>& ent = ent_scr[tid];
+        ent.resize(lists[s].size());
         for (size_t k = 0; k < ent.size(); ++k) {
             const int32_t t = lists[s][k];
             const d3 c{sph[4 * t], sph[4 * t + 1], sph[4 * t + 2]};
