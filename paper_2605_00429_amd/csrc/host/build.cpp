@@ -1013,9 +1013,19 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
         for (int32_t s = 0; s < nS; ++s) {
             if (dev_balls[s].empty()) continue;
             job.sites.push_back(s);
-            for (const Ball& b : dev_balls[s]) job.balls.insert(job.balls.end(), {b.c.x, b.c.y, b.c.z, b.r});
-            job.ball_off.push_back((int64_t)job.balls.size() / 4);
+            job.ball_off.push_back(job.ball_off.back() + (int64_t)dev_balls[s].size());
         }
+        job.balls.resize(4 * (size_t)job.ball_off.back());
+        parallel_for((int64_t)job.sites.size(), nth, [&](int64_t i, int) {
+            double* out = job.balls.data() + 4 * job.ball_off[i];
+            for (const Ball& b : dev_balls[job.sites[i]]) {
+                out[0] = b.c.x;
+                out[1] = b.c.y;
+                out[2] = b.c.z;
+                out[3] = b.r;
+                out += 4;
+            }
+        }, 1024);
         std::vector<int64_t> off;
         std::vector<int32_t> ids;
         std::vector<char> redo;
