@@ -613,7 +613,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
 
     auto t0 = clk::now();
     Bvh bvh;
-    bvh.build(T);
+    bvh.build(T, nth);
     KdTree kd;
     kd.build(P);
     std::vector<CellWork> work(nth);

@@ -2,6 +2,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 
 namespace p2m {
 
@@ -9,7 +10,7 @@ namespace {
 constexpr int kLeafTris = 4;
 }
 
-void Bvh::build(const std::vector<d3>& tri)
+void Bvh::build(const std::vector<d3>& tri, int n_threads)
 {
     tri_ = &tri;
     const int32_t n = (int32_t)(tri.size() / 3);
@@ -21,10 +22,18 @@ void Bvh::build(const std::vector<d3>& tri)
     }
     nodes_.clear();
     nodes_.reserve(2 * (size_t)n / kLeafTris + 2);
-    if (n > 0) build_rec(0, n, cen);
+    int par = 0;  // levels whose left subtree goes to a thread of its own
+    while (par < 6 && (1 << par) < n_threads) ++par;
+    if (n > 0) build_rec(0, n, cen, nodes_, par);
 }
 
-int32_t Bvh::build_rec(int32_t b, int32_t e, std::vector<d3>& cen)
+// Appends the subtree of order_[b, e) to `out` in depth-first order (a
+// node, its left subtree, its right subtree) and returns its root's index.
+// With par > 0 the two subtrees are built into their own arrays, the left
+// one on a thread, and spliced in with their indices shifted, which gives
+// the array the sequential order gives: the ranges are disjoint and each
+// split depends on its own range only.
+int32_t Bvh::build_rec(int32_t b, int32_t e, const std::vector<d3>& cen, std::vector<Node>& out, int par)
 {
     const std::vector<d3>& T = *tri_;
     Node nd;
@@ -40,11 +49,11 @@ int32_t Bvh::build_rec(int32_t b, int32_t e, std::vector<d3>& cen)
         clo = dmin3(clo, cen[t]);
         chi = dmax3(chi, cen[t]);
     }
-    const int32_t id = (int32_t)nodes_.size();
-    nodes_.push_back(nd);
+    const int32_t id = (int32_t)out.size();
+    out.push_back(nd);
     if (e - b <= kLeafTris) {
-        nodes_[id].left_or_begin = b;
-        nodes_[id].right_or_count = -(e - b);
+        out[id].left_or_begin = b;
+        out[id].right_or_count = -(e - b);
         return id;
     }
     const d3 ext = chi - clo;
@@ -52,10 +61,32 @@ int32_t Bvh::build_rec(int32_t b, int32_t e, std::vector<d3>& cen)
     const int32_t m = b + (e - b) / 2;
     std::nth_element(order_.begin() + b, order_.begin() + m, order_.begin() + e,
                      [&](int32_t i, int32_t j) { return comp(cen[i], axis) < comp(cen[j], axis); });
-    build_rec(b, m, cen);  // left child is id + 1
-    const int32_t r = build_rec(m, e, cen);
-    nodes_[id].left_or_begin = id + 1;
-    nodes_[id].right_or_count = r;
+    if (par <= 0) {
+        build_rec(b, m, cen, out, 0);  // left child is id + 1
+        const int32_t r = build_rec(m, e, cen, out, 0);
+        out[id].left_or_begin = id + 1;
+        out[id].right_or_count = r;
+        return id;
+    }
+    std::vector<Node> L, R;
+    std::thread left([&] { build_rec(b, m, cen, L, par - 1); });
+    build_rec(m, e, cen, R, par - 1);
+    left.join();
+    auto splice = [&](const std::vector<Node>& sub) {
+        const int32_t shift = (int32_t)out.size();
+        for (Node x : sub) {
+            if (x.right_or_count >= 0) {  // internal: both links are indices
+                x.left_or_begin += shift;
+                x.right_or_count += shift;
+            }
+            out.push_back(x);
+        }
+        return shift;
+    };
+    const int32_t l = splice(L);
+    const int32_t r = splice(R);
+    out[id].left_or_begin = l;
+    out[id].right_or_count = r;
     return id;
 }
 

@@ -25,8 +25,10 @@ public:
         int32_t left_or_begin;  // internal: unused (left child is next node); leaf: first slot in order()
         int32_t right_or_count; // internal: right child index; leaf: -count
     };
-    // tri: 3 vertices per triangle (FP64 copies of the FP32 input).
-    void build(const std::vector<d3>& tri);
+    // tri: 3 vertices per triangle (FP64 copies of the FP32 input).  With
+    // n_threads > 1 the top levels' subtrees are built on threads; the tree
+    // is the same.
+    void build(const std::vector<d3>& tri, int n_threads = 1);
     // Triangles (original ids) meeting the closed union of `balls`.  `stamp`
     // (size >= n triangles) and `gen` deduplicate across calls.  Stops as
     // soon as `out` holds more than `cap` entries (it is then incomplete).
@@ -38,7 +40,7 @@ public:
     const std::vector<int32_t>& order() const { return order_; }
 
 private:
-    int32_t build_rec(int32_t b, int32_t e, std::vector<d3>& cen);
+    int32_t build_rec(int32_t b, int32_t e, const std::vector<d3>& cen, std::vector<Node>& out, int par);
     static double box_d2(const Node& n, d3 q);
     const std::vector<d3>* tri_ = nullptr;
     std::vector<Node> nodes_;
