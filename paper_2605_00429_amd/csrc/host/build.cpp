@@ -615,7 +615,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
     Bvh bvh;
     bvh.build(T, nth);
     KdTree kd;
-    kd.build(P);
+    kd.build(P, nth);
     std::vector<CellWork> work(nth);
     for (auto& w : work) w.stamp.assign(nT, 0);
     const CheckFn checks = gpu_checks ? *gpu_checks
@@ -861,7 +861,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
                 std::vector<d3> PP = P;
                 PP.insert(PP.end(), aux.begin(), aux.end());
                 KdTree kd2;
-                kd2.build(PP);
+                kd2.build(PP, nth);
                 std::vector<char> drop(aux.size(), 0);
                 std::vector<int32_t> asites;
                 for (size_t i = 0; i < aux.size(); ++i)
@@ -908,7 +908,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             // Vertex cells reused from pass 1 unless an auxiliary site is
             // closer than the site to one of their corners.
             KdTree kda;
-            kda.build(aux);
+            kda.build(aux, nth);
             static const std::vector<int32_t> none;
             parallel_for(nVS, nth, [&](int64_t s, int) {
                 if (unresolved[s]) { cell_done[s] = 0; return; }
@@ -920,7 +920,7 @@ void build_host(const p2m_mesh_desc& mesh, const p2m_build_opts& o, HostStructur
             P.insert(P.end(), aux.begin(), aux.end());
             is_aux.assign(P.size(), 0);
             for (size_t i = nVS; i < P.size(); ++i) is_aux[i] = 1;
-            kd.build(P);
+            kd.build(P, nth);
         } else {
             for (int32_t s = 0; s < nVS; ++s) cell_done[s] = !unresolved[s];
         }

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <limits>
 #include <queue>
+#include <thread>
 
 namespace p2m {
 
@@ -11,7 +12,7 @@ namespace {
 constexpr int kLeaf = 8;
 }
 
-void KdTree::build(const std::vector<d3>& pts)
+void KdTree::build(const std::vector<d3>& pts, int n_threads)
 {
     static std::atomic<uint64_t> next_stamp{1};
     stamp_ = next_stamp.fetch_add(1);
@@ -21,12 +22,18 @@ void KdTree::build(const std::vector<d3>& pts)
     nodes_.clear();
     nodes_.reserve(2 * pts.size() / kLeaf + 2);
     depth_ = 0;
-    if (!pts.empty()) build_rec(0, (int32_t)pts.size(), 1);
+    int par = 0;  // levels whose left subtree goes to a thread of its own
+    while (par < 6 && (1 << par) < n_threads) ++par;
+    if (!pts.empty()) build_rec(0, (int32_t)pts.size(), 1, nodes_, depth_, par);
 }
 
-int32_t KdTree::build_rec(int32_t b, int32_t e, int depth)
+// Appends the subtree of idx_[b, e) to `out` in depth-first order and
+// returns its root's index.  With par > 0 the two subtrees are built into
+// their own arrays, the left one on a thread, and spliced in with their
+// indices shifted: the same array as the sequential order gives.
+int32_t KdTree::build_rec(int32_t b, int32_t e, int depth, std::vector<Node>& out, int& max_depth, int par)
 {
-    depth_ = std::max(depth_, depth);
+    max_depth = std::max(max_depth, depth);
     Node n;
     n.lo = {INFINITY, INFINITY, INFINITY};
     n.hi = {-INFINITY, -INFINITY, -INFINITY};
@@ -37,18 +44,42 @@ int32_t KdTree::build_rec(int32_t b, int32_t e, int depth)
     n.begin = b;
     n.end = e;
     n.left = n.right = -1;
-    int32_t id = (int32_t)nodes_.size();
-    nodes_.push_back(n);
+    int32_t id = (int32_t)out.size();
+    out.push_back(n);
     if (e - b <= kLeaf) return id;
     d3 ext = n.hi - n.lo;
     int axis = (ext.x >= ext.y && ext.x >= ext.z) ? 0 : (ext.y >= ext.z ? 1 : 2);
     int32_t m = b + (e - b) / 2;
     std::nth_element(idx_.begin() + b, idx_.begin() + m, idx_.begin() + e,
                      [&](int32_t i, int32_t j) { return comp(pts_[i], axis) < comp(pts_[j], axis); });
-    int32_t l = build_rec(b, m, depth + 1);
-    int32_t r = build_rec(m, e, depth + 1);
-    nodes_[id].left = l;
-    nodes_[id].right = r;
+    if (par <= 0) {
+        int32_t l = build_rec(b, m, depth + 1, out, max_depth, 0);
+        int32_t r = build_rec(m, e, depth + 1, out, max_depth, 0);
+        out[id].left = l;
+        out[id].right = r;
+        return id;
+    }
+    std::vector<Node> L, R;
+    int dl = 0, dr = 0;
+    std::thread left([&] { build_rec(b, m, depth + 1, L, dl, par - 1); });
+    build_rec(m, e, depth + 1, R, dr, par - 1);
+    left.join();
+    max_depth = std::max(max_depth, std::max(dl, dr));
+    auto splice = [&](const std::vector<Node>& sub) {
+        const int32_t shift = (int32_t)out.size();
+        for (Node x : sub) {
+            if (x.left >= 0) {
+                x.left += shift;
+                x.right += shift;
+            }
+            out.push_back(x);
+        }
+        return shift;
+    };
+    const int32_t l = splice(L);
+    const int32_t r = splice(R);
+    out[id].left = l;
+    out[id].right = r;
     return id;
 }
 

@@ -12,7 +12,9 @@ namespace p2m {
 
 class KdTree {
 public:
-    void build(const std::vector<d3>& pts);
+    // With n_threads > 1 the top levels' subtrees are built on threads;
+    // the tree is the same.
+    void build(const std::vector<d3>& pts, int n_threads = 1);
     // k nearest points to q (excluding index `skip`), ascending distance.
     void knn(d3 q, int k, int32_t skip, std::vector<std::pair<double, int32_t>>& out) const;
     // Nearest point to q with squared distance strictly below `limit2` whose
@@ -54,7 +56,7 @@ private:
         int32_t begin, end;   // range in idx_ (leaves)
         int32_t left, right;  // children, -1 for a leaf
     };
-    int32_t build_rec(int32_t b, int32_t e, int depth);
+    int32_t build_rec(int32_t b, int32_t e, int depth, std::vector<Node>& out, int& max_depth, int par);
     static double box_d2(const Node& n, d3 q);
     std::vector<d3> pts_;
     std::vector<int32_t> idx_;
