@@ -1928,7 +1928,7 @@ hipError_t launch_grouped(const DevMesh& m, const FwdArgs& a, void* ws, bool fus
         std::swap(vin, vout);
     }
     // the runs of each site and the work items (a site's run in pieces of
-    // at most 64 points; the item count stays on the device)
+    // at most item_lanes points; the item count stays on the device)
     fill_u32_kernel<<<grid_for(2 * n_runs, 256), 256, 0, st>>>((uint32_t*)runs, 0u, 2 * n_runs);
     run_bounds_kernel<<<grid_for(n, 256), 256, 0, st>>>(kin, n, runs);
     fill_u32_kernel<<<1, 1, 0, st>>>(cnt + n_runs, 0u, 1);
